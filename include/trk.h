@@ -1,0 +1,169 @@
+/*
+ * trk.h - C ABI of the MI355X (gfx950) tracking-chain library libtrk.so.
+ *
+ * The per-event chain is the one of Section 2.2.2 of "Track reconstruction as a
+ * service for collider physics" (arXiv:2501.05520): an embedding MLP over
+ * spacepoints, a fixed-radius neighbour graph in the embedding space, an edge
+ * filter MLP with a fixed threshold, an interaction-network edge classifier,
+ * and a score cut followed by weakly connected components that turn the kept
+ * edges into track candidates.  The lifecycle (create with configuration,
+ * weights and device; execute per request; destroy) follows the custom-backend
+ * lifecycle of Section 4.1.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: TRK_OK (0) or a negative trk_status.  trk_strerror() names it.
+ *  - Arguments are validated on the host before anything is enqueued; on error
+ *    nothing has been launched and outputs are untouched.
+ *  - Pointers named d_* are device pointers (HBM of the context's device),
+ *    owned by the caller, and must stay valid until the stream reaches the
+ *    enqueued work.  Pointers named h_* are host pointers.
+ *  - Work is enqueued on `stream` (NULL = the default stream).  Calls that
+ *    return a count to the host (h_n_edges, h_n_kept, info) synchronise the
+ *    stream before returning; the others do not.
+ *  - Float data is IEEE float32, indices int32, row-major.
+ *  - A context is used by one host thread at a time; its scratch memory is
+ *    allocated once at creation from the max_* fields, so no entry point
+ *    allocates device memory.
+ *  - Capacity overflow is never truncated silently: the call returns
+ *    TRK_E_CAPACITY and, where it has a count output, writes the required count.
+ */
+#ifndef TRK_H
+#define TRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRK_ABI_VERSION 1u
+#define TRK_WEIGHTS_MAGIC 0x5754524Bu /* "KRTW" little-endian: 'K','R','T','W' */
+
+typedef struct trk_ctx trk_ctx;
+
+typedef enum {
+  TRK_OK = 0,
+  TRK_E_INVAL = -1,     /* bad argument: NULL pointer, size out of range, unsupported width */
+  TRK_E_NOMEM = -2,     /* device allocation failed at trk_create */
+  TRK_E_CAPACITY = -3,  /* an edge count exceeds the capacity given */
+  TRK_E_DEVICE = -4,    /* a HIP runtime call failed */
+  TRK_E_WEIGHTS = -5,   /* weight blob malformed or inconsistent with the configuration */
+} trk_status;
+
+typedef enum {
+  TRK_FP32 = 0,  /* MLP and GNN matrix products in FP32 on MFMA */
+  TRK_BF16 = 1,  /* matrix products in BF16 on MFMA, FP32 accumulation; activations stored BF16 */
+} trk_precision;
+
+/* Model and sizing configuration, the analogue of a served model's config
+ * (input shape, model, device; Section 4.1).  Network shapes:
+ *   embedding  3 -> emb_hidden x emb_layers -> emb_dim        tanh on hidden layers
+ *   filter     2*emb_dim -> filt_hidden x filt_layers -> 1    tanh on hidden layers
+ *   interaction network, hidden H = gnn_hidden, gnn_iters message-passing steps:
+ *     node encoder [3,H,H], edge encoder [6,H,H], edge network [3H,H,H],
+ *     node network [2H,H,H] (tanh after every layer), output [3H,H,1].
+ * Supported: emb_hidden in {64,1024}, emb_layers >= 1, emb_dim in 1..16,
+ * filt_hidden in {64,512}, filt_layers >= 1, gnn_hidden in {32,128}, gnn_iters >= 0,
+ * 1 <= k_max <= 1024, radius > 0. */
+typedef struct {
+  uint32_t abi_version;       /* TRK_ABI_VERSION */
+  int32_t emb_hidden, emb_layers, emb_dim;
+  int32_t filt_hidden, filt_layers;
+  int32_t gnn_hidden, gnn_iters;
+  float radius;               /* fixed radius r: an edge needs d^2 < r^2 */
+  int32_t k_max;              /* at most k_max neighbours per spacepoint (nearest by (d^2, id)) */
+  float filter_cut;           /* filter keeps p_f > filter_cut */
+  float score_cut;            /* components use edges with p > score_cut */
+  int32_t precision;          /* trk_precision */
+  int64_t max_hits;           /* largest spacepoint count of one call (sum over a batch) */
+  int64_t max_cand_edges;     /* capacity of candidate edges (radius graph) */
+  int64_t max_kept_edges;     /* capacity of filtered edges (GNN input) */
+  int32_t max_events;         /* largest batch of trk_batch */
+} trk_config;
+
+/* Per-call counts reported by trk_event / trk_batch (all host memory). */
+typedef struct {
+  int64_t n_hits;
+  int64_t n_cand_edges;       /* |E_c| */
+  int64_t n_filt_edges;       /* |E_f| */
+  int64_t n_kept_edges;       /* edges with GNN score > score_cut */
+  int64_t n_saturated;        /* spacepoints with more than k_max neighbours within r */
+} trk_event_info;
+
+/* Weight blob: header of 16 uint32 (magic, abi_version, then the seven network
+ * widths emb_hidden, emb_layers, emb_dim, filt_hidden, filt_layers, gnn_hidden,
+ * gnn_iters, rest zero) followed by float32 tensors, each layer as W[fan_in][fan_out]
+ * row-major then b[fan_out], networks in the order embedding, filter, node
+ * encoder, edge encoder, edge network, node network, output head. */
+
+/* Creates a context on device `device_id`: copies the weights (the blob is read
+ * only during the call), derives the kernels' device layouts and precision
+ * copies, and allocates all scratch memory.  Errors: TRK_E_INVAL (config),
+ * TRK_E_WEIGHTS (blob), TRK_E_NOMEM, TRK_E_DEVICE. */
+int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int device_id,
+               trk_ctx** out);
+
+/* Waits for the context's work and frees everything it owns.  NULL is a no-op. */
+void trk_destroy(trk_ctx* ctx);
+
+/* Embedding (Section 2.2.2): d_emb[n][emb_dim] = MLP_emb(d_x[n][3]).  0 <= n <= max_hits. */
+int trk_embed(trk_ctx* ctx, const float* d_x, int64_t n, float* d_emb, hipStream_t stream);
+
+/* Fixed-radius graph (Section 2.2.2): candidate edges of the embedding
+ * d_emb[n][emb_dim].  Spacepoint i selects the k_max nearest j != i with
+ * d^2(i,j) < r^2 (FP32, ties by lower id); the output is the union of the
+ * selections as undirected pairs src < dst, sorted by (src, dst), written to
+ * d_src[0..E) and d_dst[0..E).  *h_n_edges receives E (synchronises).  If E > cap
+ * returns TRK_E_CAPACITY with *h_n_edges = E and the outputs undefined.
+ * h_n_saturated (optional) receives the count of spacepoints with more than k_max
+ * neighbours within r. */
+int trk_build_graph(trk_ctx* ctx, const float* d_emb, int64_t n, int32_t* d_src, int32_t* d_dst,
+                    int64_t cap, int64_t* h_n_edges, int64_t* h_n_saturated, hipStream_t stream);
+
+/* Edge filter (Section 2.2.2): p_f = sigmoid(MLP_f([emb_src, emb_dst])) for the m
+ * edges (d_src, d_dst); writes d_scores[m] when non-NULL; copies the edges with
+ * p_f > filter_cut, in input order, to d_kept_src/d_kept_dst and their count to
+ * *h_n_kept (synchronises).  Kept count > cap: TRK_E_CAPACITY with *h_n_kept set.
+ * Edge endpoints must lie in [0, n). */
+int trk_filter(trk_ctx* ctx, const float* d_emb, int64_t n, const int32_t* d_src,
+               const int32_t* d_dst, int64_t m, float* d_scores, int32_t* d_kept_src,
+               int32_t* d_kept_dst, int64_t cap, int64_t* h_n_kept, hipStream_t stream);
+
+/* Interaction network (Section 2.2.2, after Battaglia et al.): edge scores
+ * d_scores[m] in (0,1) for the m edges (d_src, d_dst) over spacepoints d_x[n][3].
+ * m <= max_kept_edges; endpoints in [0, n). */
+int trk_gnn(trk_ctx* ctx, const float* d_x, int64_t n, const int32_t* d_src, const int32_t* d_dst,
+            int64_t m, float* d_scores, hipStream_t stream);
+
+/* Score cut and weakly connected components (Section 2.2.2): over the graph of
+ * the m edges with d_scores[e] > cut (all m edges if d_scores is NULL),
+ * d_labels[i] = the smallest spacepoint id in i's component. */
+int trk_components(trk_ctx* ctx, int64_t n, const int32_t* d_src, const int32_t* d_dst,
+                   const float* d_scores, int64_t m, float cut, int32_t* d_labels,
+                   hipStream_t stream);
+
+/* The whole chain for one event (Section 2.2.2, one request of Section 4.1):
+ * d_x[n][3] -> d_labels[n], stages chained with device-resident counts and no
+ * host round trip in between.  Synchronises the stream before returning, to
+ * report overflow (TRK_E_CAPACITY) and, when info is non-NULL, the counts. */
+int trk_event(trk_ctx* ctx, const float* d_x, int64_t n, int32_t* d_labels, trk_event_info* info,
+              hipStream_t stream);
+
+/* A batch of independent events packed back to back: event b owns spacepoints
+ * [h_offsets[b], h_offsets[b+1]) of d_x.  One launch sequence serves the whole
+ * batch; no edge joins two events.  d_labels[i] is the smallest id, counted from
+ * the start of i's own event, in i's component, so each event's labels equal those
+ * of trk_event on that event alone.  infos (optional) receives one record per
+ * event.  Synchronises like trk_event. */
+int trk_batch(trk_ctx* ctx, int32_t n_events, const float* d_x, const int64_t* h_offsets,
+              int32_t* d_labels, trk_event_info* infos, hipStream_t stream);
+
+/* Static description of a status code. */
+const char* trk_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRK_H */

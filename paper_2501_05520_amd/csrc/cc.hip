@@ -1,0 +1,87 @@
+// Score cut and weakly connected components (Section 2.2.2: the GNN edge scores go
+// to a weakly-connected-components step that forms the track candidates).
+//
+// Lock-free union-find over the kept edges.  parent[] starts as the identity; an
+// edge whose score passes the cut finds the roots of its two ends and links the
+// larger root under the smaller one with a compare-and-swap that succeeds only
+// while the larger is still a root.  Every write (link or path halving) replaces
+// a parent by an ancestor, so parent[x] <= x always holds and the root of every
+// tree is its smallest member: after a final pass of pointer jumping, the label of
+// each spacepoint is the smallest id of its component, whatever the order in which
+// edges were processed.
+#include "kernels.h"
+#include "common.h"
+
+namespace {
+
+__device__ __forceinline__ int uf_find(int* parent, int x) {
+  int p = load_relaxed(&parent[x]);
+  while (p != x) {
+    const int gp = load_relaxed(&parent[p]);
+    if (gp != p) parent[x] = gp;  // path halving: gp is an ancestor of x
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ __forceinline__ void uf_union(int* parent, int a, int b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a > b) { const int t = a; a = b; b = t; }
+    // link root b under root a if b is still a root
+    const int old = atomicCAS(&parent[b], b, a);
+    if (old == b) return;
+    b = old;  // b gained a parent meanwhile: continue from there
+  }
+}
+
+__global__ void uf_init(int* parent, int n) {
+  GRID_STRIDE(i, n) parent[i] = (int)i;
+}
+
+__global__ void uf_hook(int* parent, const int* __restrict__ src, const int* __restrict__ dst,
+                        const float* __restrict__ scores, float cut, int64_t m_cap, const int* d_m, int n,
+                        int* d_kept, int* d_err) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  int kept = 0;
+  GRID_STRIDE(e, m) {
+    if (!scores || scores[e] > cut) {
+      const int a = src[e], b = dst[e];
+      if ((unsigned)a >= (unsigned)n || (unsigned)b >= (unsigned)n) {
+        if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+        continue;
+      }
+      ++kept;
+      uf_union(parent, a, b);
+    }
+  }
+  if (d_kept) {
+    kept = wave_sum(kept);
+    if (lane_id() == 0 && kept) atomicAdd(d_kept, kept);
+  }
+}
+
+__global__ void uf_compress(int* parent, int n) {
+  GRID_STRIDE(i, n) {
+    int x = (int)i;
+    int p = load_relaxed(&parent[x]);
+    while (p != x) {
+      x = p;
+      p = load_relaxed(&parent[x]);
+    }
+    parent[i] = x;
+  }
+}
+
+}  // namespace
+
+void launch_components(int n, const int* src, const int* dst, const float* scores, float cut, int64_t m_cap,
+                       const int* d_m, int* labels, int* d_kept, int* d_err, hipStream_t s) {
+  if (n <= 0) return;
+  uf_init<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
+  if (m_cap > 0) uf_hook<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n, d_kept, d_err);
+  uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
+}

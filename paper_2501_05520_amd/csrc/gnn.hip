@@ -1,0 +1,457 @@
+// Interaction-network edge classifier (Section 2.2.2, after Battaglia et al.):
+//   h0 = phi_v0(x_i),  e0 = phi_e0([x_s, x_t])
+//   for t = 1..T:  e <- e + phi_e([h_s, h_t, e]);   m_i = sum of e over edges at i;
+//                  h <- h + phi_v([h, m])
+//   p = sigmoid(phi_o([h_s, h_t, e]))
+//
+// MI355X layout.  The first layer of phi_e (and of phi_o) is factorised by its
+// three input blocks: the per-node projections [h W_a | h W_b] are computed once
+// per node by the node kernel (N x 2H) and gathered per edge, so each edge pays
+// for two H x H products instead of a 3H x H one.  Edge states e live in HBM in
+// the working precision and are rewritten in place each iteration; node states
+// stay FP32.  Aggregation is a gather, not a scatter: each node sums the states
+// of its incident edges through CSR (by source) and CSC (by destination) index
+// lists sorted by edge id, in a fixed order, so the sums are deterministic and an
+// event gives the same scores alone or batched with others.
+#include "kernels.h"
+#include "mfma_tile.h"
+#include <algorithm>
+
+namespace {
+
+constexpr int KIN = 32;  // padded width of the encoder inputs (3 or 6 features)
+
+template <class P, int H, int MT, int NW>
+struct GnnShape {
+  typedef typename P::act_t T;
+  static constexpr int LDH = H + P::PAD;
+  static constexpr int LD2 = 2 * H + P::PAD;
+  static constexpr int LDI = KIN + P::PAD;
+  static constexpr int MTW = MT / 16;
+  static constexpr int NTW = H / 16 / NW;      // n-tiles per wave for N = H
+  static constexpr int NTW2 = 2 * H / 16 / NW; // for N = 2H
+  static_assert(NTW >= 1 && H % (16 * NW) == 0, "H must split over the waves");
+};
+
+template <class P>
+__device__ __forceinline__ void load4(const typename P::act_t* p, float& a, float& b, float& c, float& d);
+template <>
+__device__ __forceinline__ void load4<PrecF32>(const float* p, float& a, float& b, float& c, float& d) {
+  const float4 v = *(const float4*)p;
+  a = v.x; b = v.y; c = v.z; d = v.w;
+}
+template <>
+__device__ __forceinline__ void load4<PrecBF16>(const __bf16* p, float& a, float& b, float& c, float& d) {
+  const bf16x4 v = *(const bf16x4*)p;
+  a = (float)v[0]; b = (float)v[1]; c = (float)v[2]; d = (float)v[3];
+}
+
+// copy rows [row0, row0 + MT) of a [rows][H] act array into LDS (zero past `rows`)
+template <class P, int H, int MT, int NT>
+__device__ __forceinline__ void stage_rows(const typename P::act_t* __restrict__ g, int64_t row0, int64_t rows,
+                                           typename P::act_t* lds, int ld) {
+  constexpr int V = 16 / (int)sizeof(typename P::act_t);  // elements per 16-byte chunk
+  constexpr int CPR = H / V;                               // chunks per row
+  for (int idx = threadIdx.x; idx < MT * CPR; idx += NT) {
+    const int m = idx / CPR, c = idx - m * CPR;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (row0 + m < rows) v = *(const uint4*)(g + (size_t)(row0 + m) * H + c * V);
+    *(uint4*)(lds + m * ld + c * V) = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node encoder: h0 = tanh(tanh(x W1 + b1) W2 + b2); proj = h0 [W_a | W_b]
+// ---------------------------------------------------------------------------
+template <class P, int H, int MT, int NW>
+__global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __restrict__ x, int n, DevLayer l1,
+                                                              DevLayer l2, DevLayer lp, float* __restrict__ h,
+                                                              typename P::act_t* __restrict__ proj) {
+  typedef GnnShape<P, H, MT, NW> S;
+  typedef typename S::T T;
+  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ __align__(16) T a1[MT * S::LDH];
+  __shared__ __align__(16) T a2[MT * S::LDH];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int ntiles = (n + MT - 1) / MT;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int row0 = t * MT;
+    for (int idx = threadIdx.x; idx < MT * P::KB; idx += blockDim.x) {
+      const int m = idx / P::KB, k = idx - m * P::KB;
+      xin[m * S::LDI + k] = P::cvt((k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f);
+    }
+    __syncthreads();
+    f32x4 acc[S::MTW][S::NTW];
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
+    tile_store_tanh<P>(acc, l1.b, a1, S::LDH, wave * S::NTW);
+    __syncthreads();
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, a1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+#pragma unroll
+    for (int j = 0; j < S::NTW; ++j) {
+      const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+      const float4 b = *(const float4*)(l2.b + nn);
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        const int m = i * 16 + r;
+        const float v0 = trk_tanh(acc[i][j][0] + b.x), v1 = trk_tanh(acc[i][j][1] + b.y);
+        const float v2 = trk_tanh(acc[i][j][2] + b.z), v3 = trk_tanh(acc[i][j][3] + b.w);
+        if (row0 + m < n) *(float4*)(h + (size_t)(row0 + m) * H + nn) = make_float4(v0, v1, v2, v3);
+        P::store4(a2 + m * S::LDH + nn, v0, v1, v2, v3);
+      }
+    }
+    __syncthreads();
+    f32x4 accp[S::MTW][S::NTW2];
+    acc_zero(accp);
+    tile_gemm<P, S::MTW, S::NTW2>(accp, a2, S::LDH, lp.w, lp.nkb, wave * S::NTW2, 0, lp.nkb);
+#pragma unroll
+    for (int j = 0; j < S::NTW2; ++j) {
+      const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        const int m = i * 16 + r;
+        if (row0 + m < n)
+          P::store4(proj + (size_t)(row0 + m) * 2 * H + nn, accp[i][j][0], accp[i][j][1], accp[i][j][2],
+                    accp[i][j][3]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// edge encoder: e0 = tanh(tanh([x_s, x_t] W1 + b1) W2 + b2)
+// ---------------------------------------------------------------------------
+template <class P, int H, int MT, int NW>
+__global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __restrict__ x, int n,
+                                                              const int* __restrict__ src, const int* __restrict__ dst,
+                                                              int64_t m_cap, const int* d_m, DevLayer l1, DevLayer l2,
+                                                              typename P::act_t* __restrict__ e, int* d_err) {
+  typedef GnnShape<P, H, MT, NW> S;
+  typedef typename S::T T;
+  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ __align__(16) T a1[MT * S::LDH];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  const int64_t ntiles = (m + MT - 1) / MT;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * MT;
+    for (int idx = threadIdx.x; idx < MT * P::KB; idx += blockDim.x) {
+      const int mm = idx / P::KB, k = idx - mm * P::KB;
+      float v = 0.f;
+      if (k < 6 && row0 + mm < m) {
+        const int node = k < 3 ? src[row0 + mm] : dst[row0 + mm];
+        if ((unsigned)node < (unsigned)n) v = x[(size_t)node * 3 + (k % 3)];
+        else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+      }
+      xin[mm * S::LDI + k] = P::cvt(v);
+    }
+    __syncthreads();
+    f32x4 acc[S::MTW][S::NTW];
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
+    tile_store_tanh<P>(acc, l1.b, a1, S::LDH, wave * S::NTW);
+    __syncthreads();
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, a1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+#pragma unroll
+    for (int j = 0; j < S::NTW; ++j) {
+      const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+      const float4 b = *(const float4*)(l2.b + nn);
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        const int64_t row = row0 + i * 16 + r;
+        if (row < m)
+          P::store4(e + (size_t)row * H + nn, trk_tanh(acc[i][j][0] + b.x), trk_tanh(acc[i][j][1] + b.y),
+                    trk_tanh(acc[i][j][2] + b.z), trk_tanh(acc[i][j][3] + b.w));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// edge step: e <- e + tanh(tanh(e W_c + b1 + P_a[s] + P_b[t]) W2 + b2)
+// edge output (OUT = true): p = sigmoid(tanh(e W_c + b1 + Q_a[s] + Q_b[t]) . w2 + b2)
+// ---------------------------------------------------------------------------
+template <class P, int H, int MT, int NW, bool OUT>
+__global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __restrict__ e,
+                                                       const typename P::act_t* __restrict__ proj,
+                                                       const int* __restrict__ src, const int* __restrict__ dst,
+                                                       int n, int64_t m_cap, const int* d_m, DevLayer lc, DevLayer l2,
+                                                       DevVec lo, float* __restrict__ scores) {
+  typedef GnnShape<P, H, MT, NW> S;
+  typedef typename S::T T;
+  __shared__ __align__(16) T et[MT * S::LDH];
+  __shared__ __align__(16) T t1[OUT ? 16 : MT * S::LDH];
+  __shared__ float zred[NW * MT];
+  __shared__ int sidx[MT], didx[MT];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  const int64_t ntiles = (m + MT - 1) / MT;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * MT;
+    stage_rows<P, H, MT, NW * 64>(e, row0, m, et, S::LDH);
+    for (int mm = threadIdx.x; mm < MT; mm += blockDim.x) {
+      int a = 0, b = 0;
+      if (row0 + mm < m) {
+        a = src[row0 + mm];
+        b = dst[row0 + mm];
+        if ((unsigned)a >= (unsigned)n) a = 0;
+        if ((unsigned)b >= (unsigned)n) b = 0;
+      }
+      sidx[mm] = a;
+      didx[mm] = b;
+    }
+    __syncthreads();
+    f32x4 acc[S::MTW][S::NTW];
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, et, S::LDH, lc.w, lc.nkb, wave * S::NTW, 0, lc.nkb);
+    float part[S::MTW];
+#pragma unroll
+    for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < S::NTW; ++j) {
+      const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+      const float4 b = *(const float4*)(lc.b + nn);
+      float4 w2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (OUT) w2 = *(const float4*)(lo.w + nn);
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        const int mm = i * 16 + r;
+        float pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+        load4<P>(proj + (size_t)sidx[mm] * 2 * H + nn, pa0, pa1, pa2, pa3);
+        load4<P>(proj + (size_t)didx[mm] * 2 * H + H + nn, pb0, pb1, pb2, pb3);
+        const float v0 = trk_tanh(acc[i][j][0] + b.x + pa0 + pb0);
+        const float v1 = trk_tanh(acc[i][j][1] + b.y + pa1 + pb1);
+        const float v2 = trk_tanh(acc[i][j][2] + b.z + pa2 + pb2);
+        const float v3 = trk_tanh(acc[i][j][3] + b.w + pa3 + pb3);
+        if (OUT)
+          part[i] += v0 * w2.x + v1 * w2.y + v2 * w2.z + v3 * w2.w;
+        else
+          P::store4(t1 + mm * S::LDH + nn, v0, v1, v2, v3);
+      }
+    }
+    if (OUT) {
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        part[i] += __shfl_xor(part[i], 16, 64);
+        part[i] += __shfl_xor(part[i], 32, 64);
+        if (g == 0) zred[wave * MT + i * 16 + r] = part[i];
+      }
+      __syncthreads();
+      for (int mm = threadIdx.x; mm < MT; mm += blockDim.x) {
+        float z = lo.b;
+        for (int w = 0; w < NW; ++w) z += zred[w * MT + mm];
+        if (row0 + mm < m) scores[row0 + mm] = trk_sigmoid(z);
+      }
+      __syncthreads();
+    } else {
+      __syncthreads();
+      acc_zero(acc);
+      tile_gemm<P, S::MTW, S::NTW>(acc, t1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+#pragma unroll
+      for (int j = 0; j < S::NTW; ++j) {
+        const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+        const float4 b = *(const float4*)(l2.b + nn);
+#pragma unroll
+        for (int i = 0; i < S::MTW; ++i) {
+          const int mm = i * 16 + r;
+          const int64_t row = row0 + mm;
+          float e0, e1, e2, e3;
+          load4<P>(et + mm * S::LDH + nn, e0, e1, e2, e3);
+          if (row < m)
+            P::store4(e + (size_t)row * H + nn, e0 + trk_tanh(acc[i][j][0] + b.x), e1 + trk_tanh(acc[i][j][1] + b.y),
+                      e2 + trk_tanh(acc[i][j][2] + b.z), e3 + trk_tanh(acc[i][j][3] + b.w));
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node step: m_i = sum of incident edge states (CSR by src, then CSC by dst, each in
+// ascending edge order); h <- h + tanh(tanh([h, m] W1 + b1) W2 + b2);
+// proj = h [W_a | W_b] for the next edge step (or the output head)
+// ---------------------------------------------------------------------------
+template <class P, int H, int MT, int NW>
+__global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ h, const typename P::act_t* __restrict__ e,
+                                                            const int* __restrict__ sptr, const int* __restrict__ sidx,
+                                                            const int* __restrict__ dptr, const int* __restrict__ didx,
+                                                            int n, DevLayer l1, DevLayer l2, DevLayer lp,
+                                                            typename P::act_t* __restrict__ proj) {
+  typedef GnnShape<P, H, MT, NW> S;
+  typedef typename S::T T;
+  constexpr int CPL = (H + 63) / 64;  // columns per lane in the aggregation
+  __shared__ __align__(16) T in[MT * S::LD2];
+  __shared__ __align__(16) T t1[MT * S::LDH];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int ntiles = (n + MT - 1) / MT;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int row0 = t * MT;
+    // aggregation and staging of [h, m]; one wave per node
+    for (int mm = wave; mm < MT; mm += NW) {
+      const int node = row0 + mm;
+      float acc[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[c] = 0.f;
+      if (node < n) {
+        for (int pass = 0; pass < 2; ++pass) {
+          const int* ptr = pass == 0 ? sptr : dptr;
+          const int* idx = pass == 0 ? sidx : didx;
+          const int b = ptr[node], end = ptr[node + 1];
+          int k = b;
+          for (; k + 4 <= end; k += 4) {
+            const int e0 = idx[k], e1 = idx[k + 1], e2 = idx[k + 2], e3 = idx[k + 3];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+              const int col = l + 64 * c;
+              if (col < H) {
+                const float v0 = (float)e[(size_t)e0 * H + col], v1 = (float)e[(size_t)e1 * H + col];
+                const float v2 = (float)e[(size_t)e2 * H + col], v3 = (float)e[(size_t)e3 * H + col];
+                acc[c] = (((acc[c] + v0) + v1) + v2) + v3;
+              }
+            }
+          }
+          for (; k < end; ++k) {
+            const int e0 = idx[k];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+              const int col = l + 64 * c;
+              if (col < H) acc[c] += (float)e[(size_t)e0 * H + col];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int col = l + 64 * c;
+        if (col < H) {
+          in[mm * S::LD2 + H + col] = P::cvt(acc[c]);
+          in[mm * S::LD2 + col] = P::cvt(node < n ? h[(size_t)node * H + col] : 0.f);
+        }
+      }
+    }
+    __syncthreads();
+    f32x4 acc[S::MTW][S::NTW];
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, in, S::LD2, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
+    tile_store_tanh<P>(acc, l1.b, t1, S::LDH, wave * S::NTW);
+    __syncthreads();
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, t1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < S::NTW; ++j) {
+      const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+      const float4 b = *(const float4*)(l2.b + nn);
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        const int mm = i * 16 + r;
+        const int node = row0 + mm;
+        float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (node < n) hv = *(const float4*)(h + (size_t)node * H + nn);
+        hv.x += trk_tanh(acc[i][j][0] + b.x);
+        hv.y += trk_tanh(acc[i][j][1] + b.y);
+        hv.z += trk_tanh(acc[i][j][2] + b.z);
+        hv.w += trk_tanh(acc[i][j][3] + b.w);
+        if (node < n) *(float4*)(h + (size_t)node * H + nn) = hv;
+        P::store4(in + mm * S::LD2 + nn, hv.x, hv.y, hv.z, hv.w);
+      }
+    }
+    __syncthreads();
+    f32x4 accp[S::MTW][S::NTW2];
+    acc_zero(accp);
+    tile_gemm<P, S::MTW, S::NTW2>(accp, in, S::LD2, lp.w, lp.nkb, wave * S::NTW2, 0, lp.nkb);
+#pragma unroll
+    for (int j = 0; j < S::NTW2; ++j) {
+      const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i) {
+        const int node = row0 + i * 16 + r;
+        if (node < n)
+          P::store4(proj + (size_t)node * 2 * H + nn, accp[i][j][0], accp[i][j][1], accp[i][j][2], accp[i][j][3]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// incidence lists: for every node, the ids of the edges whose key (src or dst)
+// is that node, ascending
+// ---------------------------------------------------------------------------
+__global__ void incidence_count(const int* __restrict__ key, int64_t m_cap, const int* d_m, int n, int* cnt) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  GRID_STRIDE(e, m) {
+    const int k = key[e];
+    if ((unsigned)k < (unsigned)n) atomicAdd(&cnt[k], 1);
+  }
+}
+__global__ void incidence_fill(const int* __restrict__ key, int64_t m_cap, const int* d_m, int n,
+                               const int* __restrict__ ptr, int* cursor, int* raw) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  GRID_STRIDE(e, m) {
+    const int k = key[e];
+    if ((unsigned)k < (unsigned)n) raw[ptr[k] + atomicAdd(&cursor[k], 1)] = (int)e;
+  }
+}
+
+template <class P, int H, int MT, int NW>
+void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap, const int* d_m,
+             float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
+  typedef typename P::act_t T;
+  T* proj = (T*)g.proj;
+  T* e = (T*)g.e;
+  // incidence lists by src and by dst
+  const int* keys[2] = {src, dst};
+  int* ptrs[2] = {g.rowptr, g.cscptr};
+  int* idxs[2] = {g.rowidx, g.cscidx};
+  const int eb = blocks_for(m_cap, 256, 2048);
+  for (int k = 0; k < 2; ++k) {
+    launch_fill_int(g.cnt, 0, n, s);
+    if (m_cap > 0) incidence_count<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, g.cnt);
+    launch_scan_excl(g.cnt, ptrs[k], n, nullptr, nullptr, g.tmp, s);
+    launch_fill_int(g.cnt, 0, n, s);
+    if (m_cap > 0) incidence_fill<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, ptrs[k], g.cnt, g.raw);
+    launch_segment_sort(ptrs[k], g.raw, idxs[k], n, s);
+  }
+  const int ngrid = (int)std::min<int64_t>((n + MT - 1) / MT, (int64_t)n_cu * 4);
+  const int64_t etiles = (m_cap + MT - 1) / MT;
+  const int egrid = (int)std::min<int64_t>(etiles, (int64_t)n_cu * 4);
+  const DevLayer& first_proj = net.iters > 0 ? net.edge_ab : net.out_ab;
+  if (ngrid > 0)
+    node_encode_kernel<P, H, MT, NW><<<ngrid, NW * 64, 0, s>>>(x, n, net.node_enc1, net.node_enc2, first_proj, g.h, proj);
+  if (egrid > 0)
+    edge_encode_kernel<P, H, MT, NW><<<egrid, NW * 64, 0, s>>>(x, n, src, dst, m_cap, d_m, net.edge_enc1,
+                                                               net.edge_enc2, e, d_err);
+  for (int it = 0; it < net.iters; ++it) {
+    if (egrid > 0)
+      edge_kernel<P, H, MT, NW, false><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
+                                                                 net.edge_2, net.out_2, nullptr);
+    const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
+    if (ngrid > 0)
+      node_step_kernel<P, H, MT, NW><<<ngrid, NW * 64, 0, s>>>(g.h, e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n,
+                                                               net.node_1, net.node_2, lp, proj);
+  }
+  if (egrid > 0)
+    edge_kernel<P, H, MT, NW, true><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,
+                                                              net.edge_2, net.out_2, scores);
+}
+
+}  // namespace
+
+int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
+               const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
+  if (n <= 0) return 0;
+  if (prec == TRK_PREC_F32) {
+    if (net.H == 128) { run_gnn<PrecF32, 128, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 32) { run_gnn<PrecF32, 32, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+  } else {
+    if (net.H == 128) { run_gnn<PrecBF16, 128, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 32) { run_gnn<PrecBF16, 32, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+  }
+  return -1;
+}

@@ -1,0 +1,110 @@
+// MFMA tile engine for the row-tile MLP kernels (gfx950, wave64).
+//
+// A layer computes out[m][n] = sum_k X[m][k] * W[k][n] for a tile of rows held in
+// LDS.  The product is issued in transposed form, D = W^T X^T, so that the 16x16
+// accumulator of a lane holds four consecutive output columns of one row:
+//   lane l, register i  ->  row m = 16*mt + (l & 15),  column n = 16*nt + 4*(l >> 4) + i.
+// Operand fragments are 16 bytes per lane for both precisions:
+//   FP32 (v_mfma_f32_16x16x4_f32, four issues per fragment): lane group g = l>>4
+//        carries k = 16*kb + 4g + s in issue s = 0..3;
+//   BF16 (v_mfma_f32_16x16x32_bf16): lane group g carries k = 32*kb + 8g + j, j = 0..7.
+// Any assignment of k to (lane group, slot) is valid as long as the weight and the
+// activation fragments agree, which lets each lane read 16 contiguous bytes of its
+// activation row from LDS.  Weights are pre-arranged on the host into "fragment
+// blocks": block (nt, kb) of a layer is 64 lanes x 16 bytes, stored at index
+// nt * nkb + kb, so that a wave fetches one block with a single coalesced 1 KB load.
+#pragma once
+#include "common.h"
+
+struct PrecF32 {
+  typedef float act_t;
+  static constexpr int KB = 16;          // k per fragment block
+  static constexpr int PAD = 4;          // row padding in elements (16 bytes)
+  static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.x), __uint_as_float(x.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.y), __uint_as_float(x.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.z), __uint_as_float(x.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.w), __uint_as_float(x.w), acc, 0, 0, 0);
+  }
+  // store four consecutive columns
+  static __device__ __forceinline__ void store4(float* p, float a, float b, float c, float d) {
+    *(float4*)p = make_float4(a, b, c, d);
+  }
+  static __device__ __forceinline__ float load1(const float* p) { return *p; }
+  static __device__ __forceinline__ float cvt(float v) { return v; }
+};
+
+struct PrecBF16 {
+  typedef __bf16 act_t;
+  static constexpr int KB = 32;
+  static constexpr int PAD = 8;
+  static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
+    bf16x8 a = __builtin_bit_cast(bf16x8, w);
+    bf16x8 b = __builtin_bit_cast(bf16x8, x);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void store4(__bf16* p, float a, float b, float c, float d) {
+    bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+    *(bf16x4*)p = v;
+  }
+  static __device__ __forceinline__ float load1(const __bf16* p) { return (float)*p; }
+  static __device__ __forceinline__ __bf16 cvt(float v) { return (__bf16)v; }
+};
+
+template <int MTW, int NTW>
+__device__ __forceinline__ void acc_zero(f32x4 (&acc)[MTW][NTW]) {
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// acc[i][j] += X[rows of m-tile i] * W[:, n-tile nt0 + j] over fragment blocks
+// kb0 .. kb0 + nkb_run - 1 of a layer with nkb blocks per n-tile.
+// xs: LDS activation tile (row-major, leading dimension ldx elements), row 0 = m-tile 0.
+template <class P, int MTW, int NTW>
+__device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
+                                          const uint4* __restrict__ wb, int nkb, int nt0, int kb0,
+                                          int nkb_run) {
+  const int l = lane_id();
+  const int g = l >> 4, r = l & 15;
+  const typename P::act_t* xl = xs + r * ldx + g * (P::KB / 4);
+  const uint4* wl = wb + (size_t)nt0 * nkb * 64 + l;
+  if (nkb_run <= 0) return;
+  // one weight fragment per n-tile in flight: the fragment of n-tile j for the next k
+  // block is requested as soon as the current one has been consumed
+  uint4 w[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) w[j] = wl[((size_t)j * nkb + kb0) * 64];
+  for (int kk = 0; kk < nkb_run; ++kk) {
+    const int kb = kb0 + kk;
+    uint4 xf[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) xf[i] = *(const uint4*)(xl + i * 16 * ldx + kb * P::KB);
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) P::mma(acc[i][j], w[j], xf[i]);
+      if (kk + 1 < nkb_run) w[j] = wl[((size_t)j * nkb + kb + 1) * 64];
+    }
+  }
+}
+
+// Epilogue: out = tanh(acc + bias) written to an LDS tile (leading dimension ldo).
+template <class P, int MTW, int NTW>
+__device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], const float* __restrict__ bias,
+                                                typename P::act_t* out, int ldo, int nt0) {
+  const int l = lane_id();
+  const int g = l >> 4, r = l & 15;
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    const int n = (nt0 + j) * 16 + 4 * g;
+    const float4 b = *(const float4*)(bias + n);
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      const f32x4 a = acc[i][j];
+      P::store4(out + (i * 16 + r) * ldo + n, trk_tanh(a[0] + b.x), trk_tanh(a[1] + b.y),
+                trk_tanh(a[2] + b.z), trk_tanh(a[3] + b.w));
+    }
+  }
+}

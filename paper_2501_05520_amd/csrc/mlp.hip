@@ -1,0 +1,215 @@
+// Fused row-tile MLP kernels: embedding over spacepoints and the edge filter
+// (Section 2.2.2: the embedding MLP maps the three spacepoint features into the
+// latent space; the filter MLP scores each candidate edge from the embeddings of
+// its two ends).  A workgroup owns a tile of MT rows; every layer of the network
+// runs on that tile with the activations resident in LDS, so hidden activations
+// never travel to HBM.  Each wave owns a slab of output columns of every layer.
+// Tiles are walked by a persistent grid whose row count may be read from device
+// memory, so a kernel can be chained behind one that produced its row count.
+#include "kernels.h"
+#include "mfma_tile.h"
+
+namespace {
+
+constexpr int KIN_MAX = 32;  // widest first-layer input: [emb_s, emb_t] with emb_dim <= 16
+
+template <class P, int W, int MT, int NW>
+struct MlpShape {
+  typedef typename P::act_t T;
+  static constexpr int LD = W + P::PAD;              // activation row stride (elements)
+  static constexpr int LDI = KIN_MAX + P::PAD;       // input row stride
+  static constexpr int MTW = MT / 16;                // m-tiles per wave (all rows)
+  static constexpr int NTW = W / 16 / NW;            // n-tiles per wave
+  static constexpr int ACT_BYTES = MT * LD * (int)sizeof(T);
+  static constexpr int RED_BYTES = NW * MT * 16 * 4;
+  static constexpr int BUF_BYTES = ACT_BYTES > RED_BYTES ? ACT_BYTES : RED_BYTES;
+  static_assert(NTW >= 1 && W % (16 * NW) == 0, "columns must split evenly over waves");
+  static_assert(BUF_BYTES + MT * LDI * (int)sizeof(T) <= 160 * 1024, "LDS budget");
+};
+
+// Embedding: emb[i][0..D) = L_out(tanh(... tanh(L_in(x_i)))).
+template <class P, int W, int MT, int NW>
+__global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict__ x, int n, DevLayer l_in,
+                                                        LayerList hid, DevLayer l_out, int D,
+                                                        float* __restrict__ emb) {
+  typedef MlpShape<P, W, MT, NW> S;
+  typedef typename S::T T;
+  __shared__ __align__(16) unsigned char buf[S::BUF_BYTES];
+  __shared__ __align__(16) T xin[MT * S::LDI];
+  T* act = (T*)buf;
+  float* red = (float*)buf;
+  const int wave = threadIdx.x >> 6;
+  const int l = lane_id(), g = l >> 4, r = l & 15;
+  const int nt0 = wave * S::NTW;
+  const int ntiles = (n + MT - 1) / MT;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int row0 = t * MT;
+    for (int idx = threadIdx.x; idx < MT * P::KB; idx += blockDim.x) {
+      const int m = idx / P::KB, k = idx - m * P::KB;
+      const float v = (k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f;
+      xin[m * S::LDI + k] = P::cvt(v);
+    }
+    __syncthreads();
+    f32x4 acc[S::MTW][S::NTW];
+    acc_zero(acc);
+    tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
+    tile_store_tanh<P>(acc, l_in.b, act, S::LD, nt0);
+    __syncthreads();
+    for (int h = 0; h < hid.n; ++h) {
+      acc_zero(acc);
+      tile_gemm<P, S::MTW, S::NTW>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
+      __syncthreads();
+      tile_store_tanh<P>(acc, hid.l[h].b, act, S::LD, nt0);
+      __syncthreads();
+    }
+    // output layer: a single 16-column tile, its k range split over the waves
+    f32x4 o[S::MTW][1];
+    acc_zero(o);
+    const int per = (l_out.nkb + NW - 1) / NW;
+    const int kb0 = wave * per;
+    const int run = min(per, l_out.nkb - kb0);
+    tile_gemm<P, S::MTW, 1>(o, act, S::LD, l_out.w, l_out.nkb, 0, kb0, run);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < S::MTW; ++i)
+      *(float4*)(red + ((wave * MT + i * 16 + r) * 16 + 4 * g)) =
+          make_float4(o[i][0][0], o[i][0][1], o[i][0][2], o[i][0][3]);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < MT * D; idx += blockDim.x) {
+      const int m = idx / D, c = idx - m * D;
+      float s = l_out.b[c];
+      for (int w = 0; w < NW; ++w) s += red[(w * MT + m) * 16 + c];
+      if (row0 + m < n) emb[(size_t)(row0 + m) * D + c] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Filter: scores[e] = sigmoid(out . tanh(L_last(... tanh(L_in([emb_src, emb_dst]))))).
+template <class P, int W, int MT, int NW>
+__global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict__ emb, int D,
+                                                         const int* __restrict__ src, const int* __restrict__ dst,
+                                                         int64_t m_host, const int* __restrict__ d_m, int64_t cap,
+                                                         DevLayer l_in, LayerList hid, DevVec out,
+                                                         float* __restrict__ scores, int n_nodes, int* d_err) {
+  typedef MlpShape<P, W, MT, NW> S;
+  typedef typename S::T T;
+  __shared__ __align__(16) unsigned char buf[S::BUF_BYTES];
+  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ float zred[NW * MT];
+  T* act = (T*)buf;
+  const int wave = threadIdx.x >> 6;
+  const int l = lane_id(), g = l >> 4, r = l & 15;
+  const int nt0 = wave * S::NTW;
+  const int64_t m = d_m ? clamp_count(d_m, cap) : m_host;
+  const int64_t ntiles = (m + MT - 1) / MT;
+  const int nlayers = 1 + hid.n;
+  const int kin = 2 * D;
+  const int kin_pad = l_in.nkb * P::KB;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * MT;
+    for (int idx = threadIdx.x; idx < MT * kin_pad; idx += blockDim.x) {
+      const int mm = idx / kin_pad, k = idx - mm * kin_pad;
+      const int64_t e = row0 + mm;
+      float v = 0.f;
+      if (e < m && k < kin) {
+        const int node = (k < D) ? src[e] : dst[e];
+        if ((unsigned)node < (unsigned)n_nodes) v = emb[(size_t)node * D + (k < D ? k : k - D)];
+        else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+      }
+      xin[mm * S::LDI + k] = P::cvt(v);
+    }
+    __syncthreads();
+    for (int layer = 0; layer < nlayers; ++layer) {
+      const DevLayer& L = layer == 0 ? l_in : hid.l[layer - 1];
+      f32x4 acc[S::MTW][S::NTW];
+      acc_zero(acc);
+      if (layer == 0)
+        tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, L.w, L.nkb, nt0, 0, L.nkb);
+      else
+        tile_gemm<P, S::MTW, S::NTW>(acc, act, S::LD, L.w, L.nkb, nt0, 0, L.nkb);
+      if (layer + 1 < nlayers) {
+        if (layer > 0) __syncthreads();
+        tile_store_tanh<P>(acc, L.b, act, S::LD, nt0);
+        __syncthreads();
+      } else {
+        // last hidden layer: fold the single-output layer into the epilogue
+        float part[S::MTW];
+#pragma unroll
+        for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
+#pragma unroll
+        for (int j = 0; j < S::NTW; ++j) {
+          const int n = (nt0 + j) * 16 + 4 * g;
+          const float4 b = *(const float4*)(L.b + n);
+          const float4 w = *(const float4*)(out.w + n);
+#pragma unroll
+          for (int i = 0; i < S::MTW; ++i) {
+            const f32x4 a = acc[i][j];
+            part[i] += trk_tanh(a[0] + b.x) * w.x + trk_tanh(a[1] + b.y) * w.y +
+                       trk_tanh(a[2] + b.z) * w.z + trk_tanh(a[3] + b.w) * w.w;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < S::MTW; ++i) {
+          part[i] += __shfl_xor(part[i], 16, 64);
+          part[i] += __shfl_xor(part[i], 32, 64);
+          if (g == 0) zred[wave * MT + i * 16 + r] = part[i];
+        }
+        __syncthreads();
+        for (int mm = threadIdx.x; mm < MT; mm += blockDim.x) {
+          float z = out.b;
+          for (int w = 0; w < NW; ++w) z += zred[w * MT + mm];
+          if (row0 + mm < m) scores[row0 + mm] = trk_sigmoid(z);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <class P, int W, int MT, int NW>
+void launch_embed_t(const float* x, int n, const DevLayer& l_in, const LayerList& hid, const DevLayer& l_out,
+                    int D, float* emb, int max_grid, hipStream_t s) {
+  const int ntiles = (n + MT - 1) / MT;
+  const int grid = ntiles < max_grid ? ntiles : max_grid;
+  if (grid <= 0) return;
+  embed_kernel<P, W, MT, NW><<<grid, NW * 64, 0, s>>>(x, n, l_in, hid, l_out, D, emb);
+}
+
+template <class P, int W, int MT, int NW>
+void launch_filter_t(const float* emb, int D, const int* src, const int* dst, int64_t m_host, const int* d_m,
+                     int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out, float* scores,
+                     int n_nodes, int* d_err, int max_grid, hipStream_t s) {
+  const int64_t m = d_m ? cap : m_host;
+  const int64_t ntiles = (m + MT - 1) / MT;
+  const int grid = (int)(ntiles < max_grid ? ntiles : max_grid);
+  if (grid <= 0) return;
+  filter_kernel<P, W, MT, NW><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
+}
+
+}  // namespace
+
+int launch_embed(int prec, int W, const float* x, int n, const DevLayer& l_in, const LayerList& hid,
+                 const DevLayer& l_out, int D, float* emb, int n_cu, hipStream_t s) {
+  if (prec == TRK_PREC_F32) {
+    if (W == 1024) { launch_embed_t<PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 64) { launch_embed_t<PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
+  } else {
+    if (W == 1024) { launch_embed_t<PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 64) { launch_embed_t<PrecBF16, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
+  }
+  return -1;
+}
+
+int launch_filter(int prec, int W, const float* emb, int D, const int* src, const int* dst, int64_t m_host,
+                  const int* d_m, int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out,
+                  float* scores, int n_nodes, int* d_err, int n_cu, hipStream_t s) {
+  if (prec == TRK_PREC_F32) {
+    if (W == 512) { launch_filter_t<PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 64) { launch_filter_t<PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
+  } else {
+    if (W == 512) { launch_filter_t<PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 64) { launch_filter_t<PrecBF16, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
+  }
+  return -1;
+}

@@ -1,0 +1,641 @@
+// C ABI of libtrk.so: context lifecycle (create / execute / destroy, after the
+// custom-backend lifecycle of Section 4.1), argument validation, the device
+// arena, weight preparation and the chaining of the stage kernels of Section 2.2.2.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/trk.h"
+#include "kernels.h"
+#include "common.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// host-side weight preparation
+// ---------------------------------------------------------------------------
+struct HostLinear {
+  int K = 0, N = 0;
+  std::vector<float> w;  // [K][N]
+  std::vector<float> b;  // [N]
+};
+
+uint16_t host_f2bf(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// fragment blocks of W[K][N]: block (nt, kb) at index nt * nkb + kb, 64 lanes x 16 bytes.
+std::vector<uint8_t> make_fragments(const float* w, int K, int N, int prec, int& nkb, int& nnt) {
+  const int KB = prec == TRK_PREC_F32 ? 16 : 32;
+  nkb = (K + KB - 1) / KB;
+  nnt = (N + 15) / 16;
+  std::vector<uint8_t> out((size_t)nkb * nnt * 64 * 16, 0);
+  for (int nt = 0; nt < nnt; ++nt)
+    for (int kb = 0; kb < nkb; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int g = lane >> 4, r = lane & 15, n = nt * 16 + r;
+        uint8_t* dstp = out.data() + (((size_t)nt * nkb + kb) * 64 + lane) * 16;
+        if (prec == TRK_PREC_F32) {
+          float v[4];
+          for (int s = 0; s < 4; ++s) {
+            const int k = kb * 16 + 4 * g + s;
+            v[s] = (k < K && n < N) ? w[(size_t)k * N + n] : 0.f;
+          }
+          memcpy(dstp, v, 16);
+        } else {
+          uint16_t v[8];
+          for (int j = 0; j < 8; ++j) {
+            const int k = kb * 32 + 8 * g + j;
+            v[j] = host_f2bf((k < K && n < N) ? w[(size_t)k * N + n] : 0.f);
+          }
+          memcpy(dstp, v, 16);
+        }
+      }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// device arena: one allocation carved into 256-byte aligned pieces
+// ---------------------------------------------------------------------------
+struct Arena {
+  std::vector<std::pair<void**, size_t>> req;
+  void* base = nullptr;
+  size_t total = 0;
+  template <class T>
+  void add(T*& p, size_t count) { req.push_back({(void**)&p, count * sizeof(T)}); }
+  void add_bytes(void*& p, size_t bytes) { req.push_back({&p, bytes}); }
+  hipError_t commit() {
+    total = 0;
+    for (auto& r : req) total += (r.second + 255) & ~(size_t)255;
+    if (total == 0) total = 256;
+    hipError_t e = hipMalloc(&base, total);
+    if (e != hipSuccess) return e;
+    size_t off = 0;
+    for (auto& r : req) {
+      *r.first = (char*)base + off;
+      off += (r.second + 255) & ~(size_t)255;
+    }
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+struct trk_ctx {
+  trk_config cfg;
+  int device = 0;
+  int n_cu = 256;
+  int prec = TRK_PREC_F32;
+  hipStream_t own_stream = nullptr;
+  // weights
+  void* wmem = nullptr;
+  DevLayer emb_in, emb_out;
+  LayerList emb_hid;
+  DevLayer filt_in;
+  LayerList filt_hid;
+  DevVec filt_out;
+  DevGNN gnn;
+  // scratch
+  Arena arena;
+  float* emb = nullptr;
+  int* cand_src = nullptr;
+  int* cand_dst = nullptr;
+  float* cand_scores = nullptr;
+  int* filt_src = nullptr;
+  int* filt_dst = nullptr;
+  float* gnn_scores = nullptr;
+  int* ev = nullptr;
+  int64_t* offs = nullptr;
+  int* dev_words = nullptr;  // [16]: 0 err bits, 1 filtered count, 2 kept count, 3.. per-event use
+  int* batch_counts = nullptr;  // [max_events][4] per-event counts
+  GraphScratch graph;
+  GnnScratch gs;
+  int* host_words = nullptr;  // pinned mirror
+};
+
+namespace {
+
+bool width_ok(int w, std::initializer_list<int> allowed) {
+  for (int a : allowed)
+    if (a == w) return true;
+  return false;
+}
+
+int validate_config(const trk_config* c) {
+  if (!c || c->abi_version != TRK_ABI_VERSION) return TRK_E_INVAL;
+  if (!width_ok(c->emb_hidden, {64, 1024}) || c->emb_layers < 1 || c->emb_layers > 7) return TRK_E_INVAL;
+  if (c->emb_dim < 1 || c->emb_dim > 16) return TRK_E_INVAL;
+  if (!width_ok(c->filt_hidden, {64, 512}) || c->filt_layers < 1 || c->filt_layers > 7) return TRK_E_INVAL;
+  if (!width_ok(c->gnn_hidden, {32, 128}) || c->gnn_iters < 0 || c->gnn_iters > 64) return TRK_E_INVAL;
+  if (!(c->radius > 0.f) || c->k_max < 1 || c->k_max > 1024) return TRK_E_INVAL;
+  if (c->precision != TRK_FP32 && c->precision != TRK_BF16) return TRK_E_INVAL;
+  if (c->max_hits < 1 || c->max_hits > (1LL << 30)) return TRK_E_INVAL;
+  if (c->max_cand_edges < 1 || c->max_cand_edges > (1LL << 31) - 1) return TRK_E_INVAL;
+  if (c->max_kept_edges < 1 || c->max_kept_edges > (1LL << 31) - 1) return TRK_E_INVAL;
+  if (c->max_events < 1 || c->max_events > 65535) return TRK_E_INVAL;
+  if (c->max_hits * (int64_t)c->k_max > (1LL << 31) - 1) return TRK_E_INVAL;
+  return TRK_OK;
+}
+
+struct BlobReader {
+  const uint8_t* p;
+  size_t left;
+  bool ok = true;
+  bool take(HostLinear& L, int K, int N) {
+    const size_t need = ((size_t)K * N + N) * sizeof(float);
+    if (!ok || left < need) return ok = false;
+    L.K = K;
+    L.N = N;
+    L.w.resize((size_t)K * N);
+    L.b.resize(N);
+    memcpy(L.w.data(), p, (size_t)K * N * 4);
+    memcpy(L.b.data(), p + (size_t)K * N * 4, (size_t)N * 4);
+    p += need;
+    left -= need;
+    return true;
+  }
+};
+
+// sub-matrix rows [r0, r0 + K) of L as a K x N layer, optional bias
+HostLinear rows_of(const HostLinear& L, int r0, int K, bool bias) {
+  HostLinear o;
+  o.K = K;
+  o.N = L.N;
+  o.w.assign(L.w.begin() + (size_t)r0 * L.N, L.w.begin() + (size_t)(r0 + K) * L.N);
+  o.b = bias ? L.b : std::vector<float>(L.N, 0.f);
+  return o;
+}
+
+// [rows a-block | rows b-block] side by side: K x 2N
+HostLinear side_by_side(const HostLinear& L, int ra, int rb, int K) {
+  HostLinear o;
+  o.K = K;
+  o.N = 2 * L.N;
+  o.w.resize((size_t)K * o.N);
+  for (int k = 0; k < K; ++k)
+    for (int n = 0; n < L.N; ++n) {
+      o.w[(size_t)k * o.N + n] = L.w[(size_t)(ra + k) * L.N + n];
+      o.w[(size_t)k * o.N + L.N + n] = L.w[(size_t)(rb + k) * L.N + n];
+    }
+  o.b.assign(o.N, 0.f);
+  return o;
+}
+
+struct WeightUpload {
+  std::vector<uint8_t> bytes;
+  struct Fix { DevLayer* L; size_t wofs, bofs; };
+  struct VecFix { DevVec* V; size_t wofs; };
+  std::vector<Fix> fixes;
+  std::vector<VecFix> vfixes;
+  size_t put(const void* src, size_t n) {
+    const size_t off = (bytes.size() + 255) & ~(size_t)255;
+    bytes.resize(off + n);
+    memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+  void layer(DevLayer& D, const HostLinear& L, int prec) {
+    D.K = L.K;
+    D.N = L.N;
+    std::vector<uint8_t> f = make_fragments(L.w.data(), L.K, L.N, prec, D.nkb, D.nnt);
+    std::vector<float> b((size_t)D.nnt * 16, 0.f);
+    for (int n = 0; n < L.N; ++n) b[n] = L.b[n];
+    const size_t wo = put(f.data(), f.size());
+    const size_t bo = put(b.data(), b.size() * 4);
+    fixes.push_back({&D, wo, bo});
+  }
+  void vec(DevVec& V, const HostLinear& L) {  // L is K x 1
+    V.K = L.K;
+    std::vector<float> w(((size_t)L.K + 15) / 16 * 16, 0.f);
+    for (int k = 0; k < L.K; ++k) w[k] = L.w[k];
+    V.b = L.b[0];
+    vfixes.push_back({&V, put(w.data(), w.size() * 4)});
+  }
+  void resolve(void* base) {
+    for (auto& f : fixes) {
+      f.L->w = (const uint4*)((char*)base + f.wofs);
+      f.L->b = (const float*)((char*)base + f.bofs);
+    }
+    for (auto& v : vfixes) v.V->w = (const float*)((char*)base + v.wofs);
+  }
+};
+
+int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
+  const trk_config& k = c->cfg;
+  if (!blob || nbytes < 64) return TRK_E_WEIGHTS;
+  uint32_t hdr[16];
+  memcpy(hdr, blob, 64);
+  if (hdr[0] != TRK_WEIGHTS_MAGIC || hdr[1] != TRK_ABI_VERSION) return TRK_E_WEIGHTS;
+  const int32_t want[7] = {k.emb_hidden, k.emb_layers, k.emb_dim, k.filt_hidden, k.filt_layers, k.gnn_hidden,
+                           k.gnn_iters};
+  for (int i = 0; i < 7; ++i)
+    if ((int32_t)hdr[2 + i] != want[i]) return TRK_E_WEIGHTS;
+  BlobReader rd{(const uint8_t*)blob + 64, nbytes - 64};
+  const int H = k.gnn_hidden, W = k.emb_hidden, F = k.filt_hidden, D = k.emb_dim;
+  std::vector<HostLinear> emb(k.emb_layers + 1), filt(k.filt_layers + 1);
+  for (int i = 0; i <= k.emb_layers; ++i)
+    rd.take(emb[i], i == 0 ? 3 : W, i == k.emb_layers ? D : W);
+  for (int i = 0; i <= k.filt_layers; ++i)
+    rd.take(filt[i], i == 0 ? 2 * D : F, i == k.filt_layers ? 1 : F);
+  HostLinear ne1, ne2, ee1, ee2, en1, en2, nn1, nn2, o1, o2;
+  rd.take(ne1, 3, H); rd.take(ne2, H, H);
+  rd.take(ee1, 6, H); rd.take(ee2, H, H);
+  rd.take(en1, 3 * H, H); rd.take(en2, H, H);
+  rd.take(nn1, 2 * H, H); rd.take(nn2, H, H);
+  rd.take(o1, 3 * H, H); rd.take(o2, H, 1);
+  if (!rd.ok || rd.left != 0) return TRK_E_WEIGHTS;
+
+  const int prec = c->prec;
+  WeightUpload up;
+  up.layer(c->emb_in, emb[0], prec);
+  c->emb_hid.n = k.emb_layers - 1;
+  for (int i = 1; i < k.emb_layers; ++i) up.layer(c->emb_hid.l[i - 1], emb[i], prec);
+  up.layer(c->emb_out, emb[k.emb_layers], prec);
+  up.layer(c->filt_in, filt[0], prec);
+  c->filt_hid.n = k.filt_layers - 1;
+  for (int i = 1; i < k.filt_layers; ++i) up.layer(c->filt_hid.l[i - 1], filt[i], prec);
+  up.vec(c->filt_out, filt[k.filt_layers]);
+  DevGNN& g = c->gnn;
+  g.H = H;
+  g.iters = k.gnn_iters;
+  up.layer(g.node_enc1, ne1, prec);
+  up.layer(g.node_enc2, ne2, prec);
+  up.layer(g.edge_enc1, ee1, prec);
+  up.layer(g.edge_enc2, ee2, prec);
+  up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec);
+  up.layer(g.edge_ab, side_by_side(en1, 0, H, H), prec);
+  up.layer(g.edge_2, en2, prec);
+  up.layer(g.node_1, nn1, prec);
+  up.layer(g.node_2, nn2, prec);
+  up.layer(g.out_c, rows_of(o1, 2 * H, H, true), prec);
+  up.layer(g.out_ab, side_by_side(o1, 0, H, H), prec);
+  up.vec(g.out_2, o2);
+  if (hipMalloc(&c->wmem, up.bytes.size()) != hipSuccess) return TRK_E_NOMEM;
+  if (hipMemcpy(c->wmem, up.bytes.data(), up.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return TRK_E_DEVICE;
+  up.resolve(c->wmem);
+  return TRK_OK;
+}
+
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1024;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+int alloc_scratch(trk_ctx* c) {
+  const trk_config& k = c->cfg;
+  const int64_t NH = k.max_hits, CC = k.max_cand_edges, CF = k.max_kept_edges;
+  const int H = k.gnn_hidden;
+  const size_t act = c->prec == TRK_PREC_F32 ? 4 : 2;
+  Arena& a = c->arena;
+  GraphScratch& g = c->graph;
+  GnnScratch& s = c->gs;
+  g.table = next_pow2(2 * NH);
+  g.stats_blocks = 256;
+  const int64_t tmp_ints = std::max({scan_tmp_ints(CC), scan_tmp_ints(CF), scan_tmp_ints(g.table), scan_tmp_ints(NH + 1)});
+  a.add(c->emb, (size_t)NH * k.emb_dim);
+  a.add(c->cand_src, CC);
+  a.add(c->cand_dst, CC);
+  a.add(c->cand_scores, CC);
+  a.add(c->filt_src, CF);
+  a.add(c->filt_dst, CF);
+  a.add(c->gnn_scores, CF);
+  a.add(c->ev, NH);
+  a.add(c->offs, (size_t)k.max_events + 1);
+  a.add(c->dev_words, 16);
+  a.add(c->batch_counts, (size_t)k.max_events * 4);
+  a.add(g.cell, NH);
+  a.add(g.bucket, NH);
+  a.add(g.sorted_id, NH);
+  a.add(g.sorted_emb, (size_t)NH * 16);
+  a.add(g.sorted_cell, NH);
+  a.add(g.cnt, NH);
+  a.add(g.thr, NH);
+  a.add(g.rowcnt, NH + 1);
+  a.add(g.rowptr, NH + 1);
+  a.add(g.cursor, NH);
+  a.add(g.unsorted, CC);
+  a.add(g.hist, g.table);
+  a.add(g.start, g.table + 1);
+  a.add(g.fill, g.table);
+  a.add(g.stats, (size_t)g.stats_blocks * 160);
+  a.add(g.basis, 64);
+  a.add(g.counters, 8);
+  a.add(g.tmp, tmp_ints);
+  a.add(s.h, (size_t)NH * H);
+  a.add_bytes(s.proj, (size_t)NH * 2 * H * act);
+  a.add_bytes(s.e, (size_t)CF * H * act);
+  a.add(s.rowptr, NH + 1);
+  a.add(s.rowidx, CF);
+  a.add(s.cscptr, NH + 1);
+  a.add(s.cscidx, CF);
+  a.add(s.raw, CF);
+  a.add(s.cnt, NH);
+  a.add(s.tmp, tmp_ints);
+  if (a.commit() != hipSuccess) return TRK_E_NOMEM;
+  if (hipHostMalloc((void**)&c->host_words, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return TRK_E_NOMEM;
+  return TRK_OK;
+}
+
+int sync_words(trk_ctx* c, hipStream_t s) {
+  // dev_words[0..8) then graph counters[0..8)
+  if (hipMemcpyAsync(c->host_words, c->dev_words, 16 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return TRK_E_DEVICE;
+  if (hipMemcpyAsync(c->host_words + 16, c->graph.counters, 8 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return TRK_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return TRK_E_DEVICE;
+  return TRK_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+int check_launch() { return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE; }
+
+// the whole chain on hits [0, n) of x; ev (nullable) gives the event of each hit
+int run_chain(trk_ctx* c, const float* x, int n, const int* ev, int* labels, hipStream_t s) {
+  const trk_config& k = c->cfg;
+  int* err = &c->dev_words[0];
+  int* n_filt = &c->dev_words[1];
+  int* n_kept = &c->dev_words[2];
+  launch_fill_int(c->dev_words, 0, 16, s);
+  if (launch_embed(c->prec, k.emb_hidden, x, n, c->emb_in, c->emb_hid, c->emb_out, k.emb_dim, c->emb, c->n_cu, s))
+    return TRK_E_INVAL;
+  launch_build_graph(c->emb, n, k.emb_dim, k.radius, k.k_max, ev, c->graph, c->cand_src, c->cand_dst,
+                     k.max_cand_edges, c->n_cu, s);
+  const int* n_cand = &c->graph.counters[0];
+  if (launch_filter(c->prec, k.filt_hidden, c->emb, k.emb_dim, c->cand_src, c->cand_dst, 0, n_cand,
+                    k.max_cand_edges, c->filt_in, c->filt_hid, c->filt_out, c->cand_scores, n, err, c->n_cu, s))
+    return TRK_E_INVAL;
+  launch_compact_edges(c->cand_scores, k.filter_cut, c->cand_src, c->cand_dst, k.max_cand_edges, n_cand, c->filt_src,
+                       c->filt_dst, k.max_kept_edges, n_filt, c->graph.tmp, s);
+  if (launch_gnn(c->prec, c->gnn, x, n, c->filt_src, c->filt_dst, k.max_kept_edges, n_filt, c->gnn_scores, c->gs,
+                 c->n_cu, err, s))
+    return TRK_E_INVAL;
+  launch_components(n, c->filt_src, c->filt_dst, c->gnn_scores, k.score_cut, k.max_kept_edges, n_filt, labels,
+                    n_kept, err, s);
+  return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* trk_strerror(int status) {
+  switch (status) {
+    case TRK_OK: return "ok";
+    case TRK_E_INVAL: return "invalid argument";
+    case TRK_E_NOMEM: return "device memory allocation failed";
+    case TRK_E_CAPACITY: return "edge count exceeds capacity";
+    case TRK_E_DEVICE: return "HIP runtime error";
+    case TRK_E_WEIGHTS: return "malformed weight blob";
+    default: return "unknown status";
+  }
+}
+
+int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int device_id, trk_ctx** out) {
+  if (!out) return TRK_E_INVAL;
+  *out = nullptr;
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device_id < 0 || device_id >= ndev) return TRK_E_INVAL;
+  DeviceGuard guard(device_id);
+  trk_ctx* c = new trk_ctx();
+  c->cfg = *cfg;
+  c->device = device_id;
+  c->prec = cfg->precision == TRK_BF16 ? TRK_PREC_BF16 : TRK_PREC_F32;
+  hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_id);
+  if (c->n_cu <= 0) c->n_cu = 256;
+  rc = load_weights(c, h_weights, nbytes);
+  if (!rc) rc = alloc_scratch(c);
+  if (rc) {
+    trk_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return TRK_OK;
+}
+
+void trk_destroy(trk_ctx* c) {
+  if (!c) return;
+  DeviceGuard guard(c->device);
+  hipDeviceSynchronize();
+  if (c->arena.base) hipFree(c->arena.base);
+  if (c->wmem) hipFree(c->wmem);
+  if (c->host_words) hipHostFree(c->host_words);
+  delete c;
+}
+
+int trk_embed(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, hipStream_t s) {
+  if (!c || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_emb))) return TRK_E_INVAL;
+  if (n == 0) return TRK_OK;
+  DeviceGuard guard(c->device);
+  if (launch_embed(c->prec, c->cfg.emb_hidden, d_x, (int)n, c->emb_in, c->emb_hid, c->emb_out, c->cfg.emb_dim, d_emb,
+                   c->n_cu, s))
+    return TRK_E_INVAL;
+  return check_launch();
+}
+
+int trk_build_graph(trk_ctx* c, const float* d_emb, int64_t n, int32_t* d_src, int32_t* d_dst, int64_t cap,
+                    int64_t* h_n_edges, int64_t* h_n_saturated, hipStream_t s) {
+  if (!c || !h_n_edges || n < 0 || n > c->cfg.max_hits || cap < 0) return TRK_E_INVAL;
+  if (n > 0 && (!d_emb || (cap > 0 && (!d_src || !d_dst)))) return TRK_E_INVAL;
+  *h_n_edges = 0;
+  if (h_n_saturated) *h_n_saturated = 0;
+  if (n == 0) return TRK_OK;
+  DeviceGuard guard(c->device);
+  const int64_t eff = std::min(cap, c->cfg.max_cand_edges);
+  launch_build_graph(d_emb, (int)n, c->cfg.emb_dim, c->cfg.radius, c->cfg.k_max, nullptr, c->graph, d_src, d_dst, eff,
+                     c->n_cu, s);
+  if (check_launch()) return TRK_E_DEVICE;
+  if (sync_words(c, s)) return TRK_E_DEVICE;
+  const int64_t total = (uint32_t)c->host_words[16];
+  *h_n_edges = total;
+  if (h_n_saturated) *h_n_saturated = c->host_words[17];
+  return total > eff ? TRK_E_CAPACITY : TRK_OK;
+}
+
+int trk_filter(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, const int32_t* d_dst, int64_t m,
+               float* d_scores, int32_t* d_kept_src, int32_t* d_kept_dst, int64_t cap, int64_t* h_n_kept,
+               hipStream_t s) {
+  if (!c || !h_n_kept || n < 0 || n > c->cfg.max_hits || m < 0 || cap < 0) return TRK_E_INVAL;
+  if (m > 0 && (!d_emb || !d_src || !d_dst)) return TRK_E_INVAL;
+  if (cap > 0 && (!d_kept_src || !d_kept_dst)) return TRK_E_INVAL;
+  if (m > c->cfg.max_cand_edges) return TRK_E_INVAL;
+  *h_n_kept = 0;
+  if (m == 0) return TRK_OK;
+  DeviceGuard guard(c->device);
+  float* scores = d_scores ? d_scores : c->cand_scores;
+  launch_fill_int(c->dev_words, 0, 16, s);
+  if (launch_filter(c->prec, c->cfg.filt_hidden, d_emb, c->cfg.emb_dim, d_src, d_dst, m, nullptr, m, c->filt_in,
+                    c->filt_hid, c->filt_out, scores, (int)n, &c->dev_words[0], c->n_cu, s))
+    return TRK_E_INVAL;
+  launch_compact_edges(scores, c->cfg.filter_cut, d_src, d_dst, m, nullptr, d_kept_src, d_kept_dst, cap,
+                       &c->dev_words[1], c->graph.tmp, s);
+  if (check_launch()) return TRK_E_DEVICE;
+  if (sync_words(c, s)) return TRK_E_DEVICE;
+  if (c->host_words[0] & TRK_ERRBIT_INDEX) return TRK_E_INVAL;
+  *h_n_kept = (uint32_t)c->host_words[1];
+  return *h_n_kept > cap ? TRK_E_CAPACITY : TRK_OK;
+}
+
+int trk_gnn(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const int32_t* d_dst, int64_t m,
+            float* d_scores, hipStream_t s) {
+  if (!c || n < 0 || n > c->cfg.max_hits || m < 0 || m > c->cfg.max_kept_edges) return TRK_E_INVAL;
+  if (n > 0 && !d_x) return TRK_E_INVAL;
+  if (m > 0 && (!d_src || !d_dst || !d_scores)) return TRK_E_INVAL;
+  if (n == 0) return m == 0 ? TRK_OK : TRK_E_INVAL;
+  DeviceGuard guard(c->device);
+  launch_fill_int(c->dev_words, 0, 16, s);
+  if (launch_gnn(c->prec, c->gnn, d_x, (int)n, d_src, d_dst, m, nullptr, d_scores, c->gs, c->n_cu, &c->dev_words[0], s))
+    return TRK_E_INVAL;
+  if (check_launch()) return TRK_E_DEVICE;
+  if (sync_words(c, s)) return TRK_E_DEVICE;
+  return (c->host_words[0] & TRK_ERRBIT_INDEX) ? TRK_E_INVAL : TRK_OK;
+}
+
+int trk_components(trk_ctx* c, int64_t n, const int32_t* d_src, const int32_t* d_dst, const float* d_scores,
+                   int64_t m, float cut, int32_t* d_labels, hipStream_t s) {
+  if (!c || n < 0 || n > c->cfg.max_hits || m < 0 || m > (1LL << 31) - 1) return TRK_E_INVAL;
+  if (n > 0 && !d_labels) return TRK_E_INVAL;
+  if (m > 0 && (!d_src || !d_dst)) return TRK_E_INVAL;
+  if (n == 0) return m == 0 ? TRK_OK : TRK_E_INVAL;
+  DeviceGuard guard(c->device);
+  launch_fill_int(c->dev_words, 0, 16, s);
+  launch_components((int)n, d_src, d_dst, d_scores, cut, m, nullptr, d_labels, nullptr, &c->dev_words[0], s);
+  if (check_launch()) return TRK_E_DEVICE;
+  if (sync_words(c, s)) return TRK_E_DEVICE;
+  return (c->host_words[0] & TRK_ERRBIT_INDEX) ? TRK_E_INVAL : TRK_OK;
+}
+
+int trk_event(trk_ctx* c, const float* d_x, int64_t n, int32_t* d_labels, trk_event_info* info, hipStream_t s) {
+  if (!c || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_labels))) return TRK_E_INVAL;
+  if (info) memset(info, 0, sizeof(*info));
+  if (n == 0) return TRK_OK;
+  DeviceGuard guard(c->device);
+  int rc = run_chain(c, d_x, (int)n, nullptr, d_labels, s);
+  if (rc) return rc;
+  if (sync_words(c, s)) return TRK_E_DEVICE;
+  const int64_t n_cand = (uint32_t)c->host_words[16];
+  const int64_t n_filt = (uint32_t)c->host_words[1];
+  if (info) {
+    info->n_hits = n;
+    info->n_cand_edges = n_cand;
+    info->n_filt_edges = n_filt;
+    info->n_kept_edges = (uint32_t)c->host_words[2];
+    info->n_saturated = c->host_words[17];
+  }
+  if (n_cand > c->cfg.max_cand_edges || n_filt > c->cfg.max_kept_edges) return TRK_E_CAPACITY;
+  if (c->host_words[0] & TRK_ERRBIT_INDEX) return TRK_E_DEVICE;
+  return TRK_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of events
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void event_ids_kernel(const int64_t* __restrict__ offs, int nev, int n, int* __restrict__ ev) {
+  GRID_STRIDE(i, n) {
+    int lo = 0, hi = nev;  // largest b with offs[b] <= i
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (offs[mid] <= i) lo = mid; else hi = mid;
+    }
+    ev[i] = lo;
+  }
+}
+
+// labels to event-local ids; per-event counts of candidate, filtered and kept edges
+__global__ void batch_finish_kernel(const int64_t* __restrict__ offs, const int* __restrict__ ev, int n,
+                                    int* __restrict__ labels) {
+  GRID_STRIDE(i, n) labels[i] -= (int)offs[ev[i]];
+}
+
+__global__ void count_edges_by_event(const int* __restrict__ src, int64_t cap, const int* d_m, const int* __restrict__ ev,
+                                     int n, const float* __restrict__ scores, float cut, int* counts, int slot) {
+  const int64_t m = d_m ? clamp_count(d_m, cap) : cap;
+  GRID_STRIDE(e, m) {
+    const int s = src[e];
+    if ((unsigned)s < (unsigned)n && (!scores || scores[e] > cut)) atomicAdd(&counts[ev[s] * 4 + slot], 1);
+  }
+}
+
+__global__ void count_saturated_by_event(const int* __restrict__ cnt, int n, int k_max, const int* __restrict__ ev,
+                                         int* counts) {
+  GRID_STRIDE(i, n) {
+    if (cnt[i] > k_max) atomicAdd(&counts[ev[i] * 4 + 3], 1);
+  }
+}
+
+}  // namespace
+
+extern "C" int trk_batch(trk_ctx* c, int32_t n_events, const float* d_x, const int64_t* h_offsets, int32_t* d_labels,
+                         trk_event_info* infos, hipStream_t s) {
+  if (!c || n_events < 0 || n_events > c->cfg.max_events || (n_events > 0 && !h_offsets)) return TRK_E_INVAL;
+  if (n_events == 0) return TRK_OK;
+  if (h_offsets[0] != 0) return TRK_E_INVAL;
+  for (int b = 0; b < n_events; ++b)
+    if (h_offsets[b + 1] < h_offsets[b]) return TRK_E_INVAL;
+  const int64_t n = h_offsets[n_events];
+  if (n > c->cfg.max_hits || (n > 0 && (!d_x || !d_labels))) return TRK_E_INVAL;
+  if (infos) memset(infos, 0, sizeof(trk_event_info) * n_events);
+  if (n == 0) return TRK_OK;
+  DeviceGuard guard(c->device);
+  if (hipMemcpyAsync(c->offs, h_offsets, sizeof(int64_t) * (n_events + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+    return TRK_E_DEVICE;
+  event_ids_kernel<<<blocks_for(n, 256), 256, 0, s>>>(c->offs, n_events, (int)n, c->ev);
+  int rc = run_chain(c, d_x, (int)n, c->ev, d_labels, s);
+  if (rc) return rc;
+  if (infos) {
+    launch_fill_int(c->batch_counts, 0, (int64_t)n_events * 4, s);
+    const trk_config& k = c->cfg;
+    const int eb = blocks_for(k.max_cand_edges, 256, 2048);
+    count_edges_by_event<<<eb, 256, 0, s>>>(c->cand_src, k.max_cand_edges, &c->graph.counters[0], c->ev, (int)n,
+                                            nullptr, 0.f, c->batch_counts, 0);
+    count_edges_by_event<<<eb, 256, 0, s>>>(c->filt_src, k.max_kept_edges, &c->dev_words[1], c->ev, (int)n, nullptr,
+                                            0.f, c->batch_counts, 1);
+    count_edges_by_event<<<eb, 256, 0, s>>>(c->filt_src, k.max_kept_edges, &c->dev_words[1], c->ev, (int)n,
+                                            c->gnn_scores, k.score_cut, c->batch_counts, 2);
+    count_saturated_by_event<<<blocks_for(n, 256), 256, 0, s>>>(c->graph.cnt, (int)n, k.k_max, c->ev,
+                                                                 c->batch_counts);
+  }
+  batch_finish_kernel<<<blocks_for(n, 256), 256, 0, s>>>(c->offs, c->ev, (int)n, d_labels);
+  if (check_launch()) return TRK_E_DEVICE;
+  std::vector<int> counts(infos ? (size_t)n_events * 4 : 0);
+  if (infos && hipMemcpyAsync(counts.data(), c->batch_counts, counts.size() * sizeof(int), hipMemcpyDeviceToHost, s) !=
+                   hipSuccess)
+    return TRK_E_DEVICE;
+  if (sync_words(c, s)) return TRK_E_DEVICE;
+  const int64_t n_cand = (uint32_t)c->host_words[16];
+  const int64_t n_filt = (uint32_t)c->host_words[1];
+  if (infos)
+    for (int b = 0; b < n_events; ++b) {
+      infos[b].n_hits = h_offsets[b + 1] - h_offsets[b];
+      infos[b].n_cand_edges = counts[b * 4 + 0];
+      infos[b].n_filt_edges = counts[b * 4 + 1];
+      infos[b].n_kept_edges = counts[b * 4 + 2];
+      infos[b].n_saturated = counts[b * 4 + 3];
+    }
+  if (n_cand > c->cfg.max_cand_edges || n_filt > c->cfg.max_kept_edges) return TRK_E_CAPACITY;
+  if (c->host_words[0] & TRK_ERRBIT_INDEX) return TRK_E_DEVICE;
+  return TRK_OK;
+}

@@ -1,0 +1,287 @@
+"""Python binding of libtrk.so (ctypes).  Functions carry the C names and only
+marshal arguments: torch device tensors become device pointers, the current HIP
+stream is passed along, and status codes become exceptions.  Every step of the
+tracking chain runs inside the library's HIP kernels; there is no Python or CPU
+fallback, and loading fails loudly when the library is missing."""
+import ctypes
+import os
+import struct
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtrk.so")
+
+TRK_ABI_VERSION = 1
+TRK_WEIGHTS_MAGIC = 0x5754524B
+TRK_FP32, TRK_BF16 = 0, 1
+STATUS = {0: "TRK_OK", -1: "TRK_E_INVAL", -2: "TRK_E_NOMEM", -3: "TRK_E_CAPACITY",
+          -4: "TRK_E_DEVICE", -5: "TRK_E_WEIGHTS"}
+EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_filter", "trk_gnn",
+           "trk_components", "trk_event", "trk_batch", "trk_strerror")
+
+
+class TrkError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+
+
+class trk_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32),
+                ("emb_hidden", ctypes.c_int32), ("emb_layers", ctypes.c_int32), ("emb_dim", ctypes.c_int32),
+                ("filt_hidden", ctypes.c_int32), ("filt_layers", ctypes.c_int32),
+                ("gnn_hidden", ctypes.c_int32), ("gnn_iters", ctypes.c_int32),
+                ("radius", ctypes.c_float), ("k_max", ctypes.c_int32),
+                ("filter_cut", ctypes.c_float), ("score_cut", ctypes.c_float),
+                ("precision", ctypes.c_int32),
+                ("max_hits", ctypes.c_int64), ("max_cand_edges", ctypes.c_int64),
+                ("max_kept_edges", ctypes.c_int64), ("max_events", ctypes.c_int32)]
+
+
+class trk_event_info(ctypes.Structure):
+    _fields_ = [("n_hits", ctypes.c_int64), ("n_cand_edges", ctypes.c_int64),
+                ("n_filt_edges", ctypes.c_int64), ("n_kept_edges", ctypes.c_int64),
+                ("n_saturated", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libtrk.so not found at {LIB_PATH}: build it with "
+                               "`python -m paper_2501_05520_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, F, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_int32
+        L.trk_create.argtypes = [ctypes.POINTER(trk_config), P, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(P)]
+        L.trk_destroy.argtypes = [P]
+        L.trk_destroy.restype = None
+        L.trk_embed.argtypes = [P, P, I64, P, P]
+        L.trk_build_graph.argtypes = [P, P, I64, P, P, I64, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
+        L.trk_filter.argtypes = [P, P, I64, P, P, I64, P, P, P, I64, ctypes.POINTER(I64), P]
+        L.trk_gnn.argtypes = [P, P, I64, P, P, I64, P, P]
+        L.trk_components.argtypes = [P, I64, P, P, P, I64, F, P, P]
+        L.trk_event.argtypes = [P, P, I64, P, ctypes.POINTER(trk_event_info), P]
+        L.trk_batch.argtypes = [P, I32, P, P, P, ctypes.POINTER(trk_event_info), P]
+        L.trk_strerror.argtypes = [ctypes.c_int]
+        L.trk_strerror.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("trk_destroy", "trk_strerror"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise TrkError(rc, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# configuration and weights
+# ---------------------------------------------------------------------------
+def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max_kept_edges=None, max_events=1):
+    """trk_config from an object with the network and pipeline attributes
+    (emb_hidden, emb_layers, emb_dim, filt_hidden, filt_layers, gnn_hidden,
+    gnn_iters, radius, k_max, filter_cut, score_cut)."""
+    if isinstance(precision, str):
+        precision = {"fp32": TRK_FP32, "bf16": TRK_BF16}[precision]
+    max_hits = int(max_hits)
+    cand = int(max_cand_edges if max_cand_edges is not None else max_hits * cfg.k_max)
+    kept = int(max_kept_edges if max_kept_edges is not None else cand)
+    return trk_config(TRK_ABI_VERSION, cfg.emb_hidden, cfg.emb_layers, cfg.emb_dim, cfg.filt_hidden,
+                      cfg.filt_layers, cfg.gnn_hidden, cfg.gnn_iters, float(cfg.radius), cfg.k_max,
+                      float(cfg.filter_cut), float(cfg.score_cut), int(precision), max_hits, cand, kept,
+                      int(max_events))
+
+
+NET_ORDER = ("emb", "filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
+
+
+def pack_weights(cfg, nets):
+    """Weight blob of the C ABI: 16 uint32 header, then every layer's W[in][out]
+    and b[out] as float32, networks in NET_ORDER."""
+    hdr = [TRK_WEIGHTS_MAGIC, TRK_ABI_VERSION, cfg.emb_hidden, cfg.emb_layers, cfg.emb_dim, cfg.filt_hidden,
+           cfg.filt_layers, cfg.gnn_hidden, cfg.gnn_iters] + [0] * 7
+    parts = [struct.pack("<16I", *hdr)]
+    for name in NET_ORDER:
+        for w, b in nets[name]:
+            parts.append(np.ascontiguousarray(w, dtype=np.float32).tobytes())
+            parts.append(np.ascontiguousarray(b, dtype=np.float32).tobytes())
+    return b"".join(parts)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def trk_create(config, weights_blob, device=0):
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(weights_blob, len(weights_blob))
+    _check(lib().trk_create(ctypes.byref(config), buf, len(weights_blob), int(device), ctypes.byref(h)),
+           "trk_create")
+    return h
+
+
+def trk_destroy(ctx):
+    lib().trk_destroy(ctx)
+
+
+def trk_embed(ctx, x, emb, stream=None):
+    _check(lib().trk_embed(ctx, _ptr(x), x.shape[0], _ptr(emb), _stream(stream)), "trk_embed")
+
+
+def trk_build_graph(ctx, emb, src, dst, stream=None):
+    ne, ns = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().trk_build_graph(ctx, _ptr(emb), emb.shape[0], _ptr(src), _ptr(dst), src.numel(),
+                               ctypes.byref(ne), ctypes.byref(ns), _stream(stream))
+    if rc == -3:
+        raise TrkError(rc, f"trk_build_graph (needs {ne.value} edges)")
+    _check(rc, "trk_build_graph")
+    return ne.value, ns.value
+
+
+def trk_filter(ctx, emb, src, dst, scores, kept_src, kept_dst, stream=None):
+    nk = ctypes.c_int64()
+    rc = lib().trk_filter(ctx, _ptr(emb), emb.shape[0], _ptr(src), _ptr(dst), src.numel(), _ptr(scores),
+                          _ptr(kept_src), _ptr(kept_dst), kept_src.numel(), ctypes.byref(nk), _stream(stream))
+    if rc == -3:
+        raise TrkError(rc, f"trk_filter (needs {nk.value} kept edges)")
+    _check(rc, "trk_filter")
+    return nk.value
+
+
+def trk_gnn(ctx, x, src, dst, scores, stream=None):
+    _check(lib().trk_gnn(ctx, _ptr(x), x.shape[0], _ptr(src), _ptr(dst), src.numel(), _ptr(scores),
+                         _stream(stream)), "trk_gnn")
+
+
+def trk_components(ctx, n, src, dst, scores, cut, labels, stream=None):
+    _check(lib().trk_components(ctx, int(n), _ptr(src), _ptr(dst), _ptr(scores), src.numel(), float(cut),
+                                _ptr(labels), _stream(stream)), "trk_components")
+
+
+def trk_event(ctx, x, labels, stream=None):
+    info = trk_event_info()
+    _check(lib().trk_event(ctx, _ptr(x), x.shape[0], _ptr(labels), ctypes.byref(info), _stream(stream)),
+           "trk_event")
+    return info.as_dict()
+
+
+def trk_batch(ctx, x, offsets, labels, stream=None):
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    nev = offs.size - 1
+    infos = (trk_event_info * max(nev, 1))()
+    _check(lib().trk_batch(ctx, nev, _ptr(x), offs.ctypes.data_as(ctypes.c_void_p), _ptr(labels), infos,
+                           _stream(stream)), "trk_batch")
+    return [infos[i].as_dict() for i in range(nev)]
+
+
+def trk_strerror(status):
+    return lib().trk_strerror(int(status)).decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper owning a context and its output buffers
+# ---------------------------------------------------------------------------
+class Pipeline:
+    """A context plus allocation of outputs; each method returns torch tensors."""
+
+    def __init__(self, cfg, nets, precision="fp32", device=0, max_hits=None, max_cand_edges=None,
+                 max_kept_edges=None, max_events=1):
+        self.cfg = cfg
+        self.device = torch.device("cuda", device)
+        self.config = make_config(cfg, precision, max_hits, max_cand_edges, max_kept_edges, max_events)
+        self.ctx = trk_create(self.config, pack_weights(cfg, nets), device)
+
+    def close(self):
+        if self.ctx is not None:
+            trk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, a):
+        if not torch.is_tensor(a):
+            a = torch.as_tensor(np.asarray(a, dtype=np.float32))
+        return a.to(device=self.device, dtype=torch.float32).contiguous()
+
+    def _i32(self, a):
+        if not torch.is_tensor(a):
+            a = torch.as_tensor(np.asarray(a, dtype=np.int64))
+        return a.to(device=self.device, dtype=torch.int32).contiguous()
+
+    def embed(self, x):
+        x = self._f32(x)
+        emb = torch.empty((x.shape[0], self.cfg.emb_dim), dtype=torch.float32, device=self.device)
+        trk_embed(self.ctx, x, emb)
+        return emb
+
+    def build_graph(self, emb, cap=None):
+        emb = self._f32(emb)
+        cap = int(cap if cap is not None else self.config.max_cand_edges)
+        src = torch.empty(cap, dtype=torch.int32, device=self.device)
+        dst = torch.empty(cap, dtype=torch.int32, device=self.device)
+        ne, ns = trk_build_graph(self.ctx, emb, src, dst)
+        return src[:ne], dst[:ne], ns
+
+    def filter(self, emb, src, dst, cap=None):
+        emb, src, dst = self._f32(emb), self._i32(src), self._i32(dst)
+        m = src.numel()
+        cap = int(cap if cap is not None else m)
+        scores = torch.empty(m, dtype=torch.float32, device=self.device)
+        ks = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)[:cap]
+        kd = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)[:cap]
+        nk = trk_filter(self.ctx, emb, src, dst, scores, ks, kd)
+        return scores, ks[:nk], kd[:nk]
+
+    def gnn(self, x, src, dst):
+        x, src, dst = self._f32(x), self._i32(src), self._i32(dst)
+        scores = torch.empty(src.numel(), dtype=torch.float32, device=self.device)
+        trk_gnn(self.ctx, x, src, dst, scores)
+        return scores
+
+    def components(self, n, src, dst, scores=None, cut=0.5):
+        src, dst = self._i32(src), self._i32(dst)
+        scores = None if scores is None else self._f32(scores)
+        labels = torch.empty(max(int(n), 1), dtype=torch.int32, device=self.device)[:int(n)]
+        trk_components(self.ctx, n, src, dst, scores, cut, labels)
+        return labels
+
+    def event(self, x):
+        x = self._f32(x)
+        labels = torch.empty(max(x.shape[0], 1), dtype=torch.int32, device=self.device)[:x.shape[0]]
+        info = trk_event(self.ctx, x, labels)
+        return labels, info
+
+    def batch(self, x, offsets):
+        x = self._f32(x)
+        labels = torch.empty(max(x.shape[0], 1), dtype=torch.int32, device=self.device)[:x.shape[0]]
+        infos = trk_batch(self.ctx, x, offsets, labels)
+        return labels, infos
