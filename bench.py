@@ -1,0 +1,190 @@
+"""Throughput benchmark of the tracking chain on one MI355X.
+
+Workload: synthetic pile-up-200 events (200 overlaid collisions x 50 helical
+tracks x 10 barrel layers + 10 % noise = 110,000 hits, event seeds 200-209),
+the full-size network (embedding 3->3x1024->12, radius 0.2, <= 256 neighbours,
+filter 24->3x512->1, interaction network H=128 with 8 iterations), seeded
+random-init weights (seed 0).  A step is one event through the whole chain
+(trk_event: embedding, radius graph, filter, interaction network, score cut and
+components), inputs resident in HBM before the timed region.  Prints one JSON
+line.  The FP64 CPU oracle is timed on a bounded sample as a reference point.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FILTER_FLOP_PER_EDGE = 2 * (2 * 512 * 512 + 512)     # hidden 512x512 layers + output dot
+EMBED_FLOP_PER_HIT = 2 * (3 * 1024 + 2 * 1024 * 1024 + 1024 * 12)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+EVENT_SEEDS = list(range(200, 210))
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    p.add_argument("--no-variant", action="store_true", help="skip the BF16 comparison run")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
+    return p.parse_args()
+
+
+def run_precision(prec, cfg, nets, xs, steps, warmup, torch, trk):
+    max_hits = max(x.shape[0] for x in xs)
+    pipe = trk.Pipeline(cfg, nets, prec, max_hits=max_hits, stage_timing=True)
+    dev = [torch.as_tensor(x).cuda() for x in xs]
+    labels = [torch.empty(x.shape[0], dtype=torch.int32, device="cuda") for x in xs]
+    for i in range(warmup):
+        k = i % len(dev)
+        trk.trk_event(pipe.ctx, dev[k], labels[k])
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        k = i % len(dev)
+        s = time.perf_counter()
+        infos.append(trk.trk_event(pipe.ctx, dev[k], labels[k]))
+        lat.append(time.perf_counter() - s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out_labels = [l.cpu().numpy() for l in labels]
+    pipe.close()
+    return wall, np.array(lat), infos, out_labels
+
+
+def stage_means(infos):
+    keys = infos[0]["stage_ms"].keys()
+    return {k: float(np.mean([i["stage_ms"][k] for i in infos])) for k in keys}
+
+
+def agreement(la, lb, min_hits=3):
+    """hit-level label agreement and exact-match Jaccard of candidates (>= min_hits)"""
+    hit = float(np.mean(la == lb))
+
+    def cands(lab):
+        order = np.argsort(lab, kind="stable")
+        ls = lab[order]
+        cuts = np.flatnonzero(np.diff(ls)) + 1
+        return {tuple(g.tolist()) for g in np.split(order, cuts) if len(g) >= min_hits}
+
+    ca, cb = cands(la), cands(lb)
+    u = ca | cb
+    return hit, (len(ca & cb) / len(u) if u else 1.0)
+
+
+def cpu_baseline(cfg, nets, x):
+    """FP64 oracle on a bounded sample of one event, scaled to events/s:
+    embedding on 1/8 of the hits, the radius graph in full, the filter on 1/16
+    of the candidate edges, the interaction network on all nodes with 1/16 of
+    the filtered edges minus its cost with no edges (its cost is linear in
+    nodes and edges), components in full."""
+    import oracle
+    t = {}
+    n = x.shape[0]
+    s = time.perf_counter(); emb8 = oracle.embed(x[: n // 8], nets); t["embed"] = (time.perf_counter() - s) * 8
+    emb = oracle.embed(x, nets)          # untimed: the graph needs the whole embedding
+    s = time.perf_counter(); src, dst, _ = oracle.radius_graph(emb, np.float32(cfg.radius), cfg.k_max)
+    t["graph"] = time.perf_counter() - s
+    m16 = src.size // 16
+    s = time.perf_counter(); pf16 = oracle.filter_scores(emb, src[:m16], dst[:m16], nets)
+    t["filter"] = (time.perf_counter() - s) * 16
+    pf = pf16  # the kept edges of the sample feed the GNN timing below
+    fs, fd = oracle.filter_edges(pf, src[:m16], dst[:m16], np.float32(cfg.filter_cut))
+    e_f = int(fs.size) * 16
+    s = time.perf_counter(); oracle.interaction_network(x, fs[:0], fd[:0], nets, cfg.gnn_iters)
+    t0 = time.perf_counter() - s
+    s = time.perf_counter(); p = oracle.interaction_network(x, fs, fd, nets, cfg.gnn_iters)
+    t1 = time.perf_counter() - s
+    t["gnn"] = t0 + (t1 - t0) * 16
+    s = time.perf_counter(); oracle.components(n, fs, fd, p, np.float32(cfg.score_cut)); t["components"] = time.perf_counter() - s
+    total = sum(t.values())
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": 1.0 / total, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": (f"one mu=200 event ({n} hits, {src.size} candidate edges, ~{e_f} filtered): embedding on "
+                       "1/8 of hits, radius graph in full, filter on 1/16 of candidate edges, GNN on all nodes with "
+                       "1/16 of filtered edges (edge part scaled x16), components in full; FP64 NumPy"),
+            "stage_s": {k: round(v, 3) for k, v in t.items()}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the tracking chain shards by whole events with no exchange "
+              f"between GPUs, and this build measures a single MI355X (--gpus {args.gpus} requested)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from gen import MU200, make_weights, generate_event
+    from paper_2501_05520_amd import trk
+
+    cfg = MU200
+    nets = make_weights(cfg, 0)
+    evs = [generate_event(s, cfg.n_collisions) for s in EVENT_SEEDS[: args.events]]
+    xs = [e.x for e in evs]
+
+    wall, lat, infos, labels = run_precision(args.precision, cfg, nets, xs, args.steps, args.warmup, torch, trk)
+    st = stage_means(infos)
+    n_cand = float(np.mean([i["n_cand_edges"] for i in infos]))
+    filt_tflops = n_cand * FILTER_FLOP_PER_EDGE / (st["filter"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    value = args.steps / wall
+    result = {
+        "metric": "events/s and p50/p99 latency per mu=200 event; per-stage MFMA/HBM roofline %",
+        "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "bf16",
+        "data": "synthetic helical-track events (seeded), random-init weights (seed 0)",
+        "config": {"workload": "mu200 event: 110000 hits, emb 3-1024x3-12, r=0.2 K=256, filter 24-512x3-1, "
+                               "IN H=128 T=8, trk_event per event", "events": len(xs),
+                   "precision": args.precision},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+        "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "counts": {"n_hits": int(np.mean([i["n_hits"] for i in infos])), "n_cand_edges": int(n_cand),
+                   "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in infos])),
+                   "n_kept_edges": int(np.mean([i["n_kept_edges"] for i in infos])),
+                   "n_saturated": int(np.mean([i["n_saturated"] for i in infos]))},
+        "roofline": {"kernel": "filter_kernel", "bound": "mfma", "achieved": round(filt_tflops, 2),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(filt_tflops / peak, 4), "traffic": None,
+                     "flop_per_edge": FILTER_FLOP_PER_EDGE},
+        "stage_roofline": {
+            "embed": {"bound": "mfma", "frac": round(
+                int(np.mean([i["n_hits"] for i in infos])) * EMBED_FLOP_PER_HIT / (st["embed"] * 1e-3) / 1e12 / peak, 4)},
+            "filter": {"bound": "mfma", "frac": round(filt_tflops / peak, 4)},
+        },
+    }
+    if not args.no_variant:
+        other = "bf16" if args.precision == "fp32" else "fp32"
+        w2, lat2, inf2, lab2 = run_precision(other, cfg, nets, xs, args.steps, args.warmup, torch, trk)
+        agr = [agreement(a, b) for a, b in zip(labels, lab2)]
+        st2 = stage_means(inf2)
+        nc2 = float(np.mean([i["n_cand_edges"] for i in inf2]))
+        result["variant"] = {
+            "precision": other, "value": round(args.steps / w2, 3), "unit": "events/s",
+            "latency_ms": {"p50": round(float(np.percentile(lat2, 50)) * 1e3, 3),
+                           "p99": round(float(np.percentile(lat2, 99)) * 1e3, 3)},
+            "stage_ms": {k: round(v, 4) for k, v in st2.items()},
+            "filter_tflops": round(nc2 * FILTER_FLOP_PER_EDGE / (st2["filter"] * 1e-3) / 1e12, 2),
+            "hit_agreement_vs_primary": round(float(np.mean([a[0] for a in agr])), 5),
+            "candidate_jaccard_vs_primary": round(float(np.mean([a[1] for a in agr])), 5),
+            "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
+        }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(cfg, nets, xs[0])
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

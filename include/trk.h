@@ -81,6 +81,7 @@ typedef struct {
   int64_t max_cand_edges;     /* capacity of candidate edges (radius graph) */
   int64_t max_kept_edges;     /* capacity of filtered edges (GNN input) */
   int32_t max_events;         /* largest batch of trk_batch */
+  int32_t stage_timing;       /* non-zero: trk_event / trk_batch time each stage with HIP events */
 } trk_config;
 
 /* Per-call counts reported by trk_event / trk_batch (all host memory). */
@@ -90,6 +91,10 @@ typedef struct {
   int64_t n_filt_edges;       /* |E_f| */
   int64_t n_kept_edges;       /* edges with GNN score > score_cut */
   int64_t n_saturated;        /* spacepoints with more than k_max neighbours within r */
+  /* with stage_timing: milliseconds per stage, measured on the stream:
+   * 0 embedding, 1 radius graph, 2 filter MLP, 3 filter cut (compaction),
+   * 4 interaction network, 5 score cut + components; zero otherwise */
+  float stage_ms[8];
 } trk_event_info;
 
 /* Weight blob: header of 16 uint32 (magic, abi_version, then the seven network

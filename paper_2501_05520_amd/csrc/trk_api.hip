@@ -118,6 +118,8 @@ struct trk_ctx {
   GraphScratch graph;
   GnnScratch gs;
   int* host_words = nullptr;  // pinned mirror
+  hipEvent_t ev_stage[8] = {};
+  bool timing = false;
 };
 
 namespace {
@@ -344,6 +346,15 @@ int alloc_scratch(trk_ctx* c) {
   return TRK_OK;
 }
 
+void read_stage_times(trk_ctx* c, float* out) {
+  for (int i = 0; i < 8; ++i) out[i] = 0.f;
+  if (!c->timing) return;
+  for (int i = 0; i < 6; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_stage[i], c->ev_stage[i + 1]) == hipSuccess) out[i] = ms;
+  }
+}
+
 int sync_words(trk_ctx* c, hipStream_t s) {
   // dev_words[0..8) then graph counters[0..8)
   if (hipMemcpyAsync(c->host_words, c->dev_words, 16 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -373,22 +384,32 @@ int run_chain(trk_ctx* c, const float* x, int n, const int* ev, int* labels, hip
   int* err = &c->dev_words[0];
   int* n_filt = &c->dev_words[1];
   int* n_kept = &c->dev_words[2];
+  auto mark = [&](int i) {
+    if (c->timing) hipEventRecord(c->ev_stage[i], s);
+  };
   launch_fill_int(c->dev_words, 0, 16, s);
+  mark(0);
   if (launch_embed(c->prec, k.emb_hidden, x, n, c->emb_in, c->emb_hid, c->emb_out, k.emb_dim, c->emb, c->n_cu, s))
     return TRK_E_INVAL;
+  mark(1);
   launch_build_graph(c->emb, n, k.emb_dim, k.radius, k.k_max, ev, c->graph, c->cand_src, c->cand_dst,
                      k.max_cand_edges, c->n_cu, s);
+  mark(2);
   const int* n_cand = &c->graph.counters[0];
   if (launch_filter(c->prec, k.filt_hidden, c->emb, k.emb_dim, c->cand_src, c->cand_dst, 0, n_cand,
                     k.max_cand_edges, c->filt_in, c->filt_hid, c->filt_out, c->cand_scores, n, err, c->n_cu, s))
     return TRK_E_INVAL;
+  mark(3);
   launch_compact_edges(c->cand_scores, k.filter_cut, c->cand_src, c->cand_dst, k.max_cand_edges, n_cand, c->filt_src,
                        c->filt_dst, k.max_kept_edges, n_filt, c->graph.tmp, s);
+  mark(4);
   if (launch_gnn(c->prec, c->gnn, x, n, c->filt_src, c->filt_dst, k.max_kept_edges, n_filt, c->gnn_scores, c->gs,
                  c->n_cu, err, s))
     return TRK_E_INVAL;
+  mark(5);
   launch_components(n, c->filt_src, c->filt_dst, c->gnn_scores, k.score_cut, k.max_kept_edges, n_filt, labels,
                     n_kept, err, s);
+  mark(6);
   return check_launch();
 }
 
@@ -424,6 +445,9 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
   if (c->n_cu <= 0) c->n_cu = 256;
   rc = load_weights(c, h_weights, nbytes);
   if (!rc) rc = alloc_scratch(c);
+  c->timing = cfg->stage_timing != 0;
+  for (int i = 0; i < 8 && !rc && c->timing; ++i)
+    if (hipEventCreate(&c->ev_stage[i]) != hipSuccess) rc = TRK_E_DEVICE;
   if (rc) {
     trk_destroy(c);
     return rc;
@@ -439,6 +463,8 @@ void trk_destroy(trk_ctx* c) {
   if (c->arena.base) hipFree(c->arena.base);
   if (c->wmem) hipFree(c->wmem);
   if (c->host_words) hipHostFree(c->host_words);
+  for (int i = 0; i < 8; ++i)
+    if (c->ev_stage[i]) hipEventDestroy(c->ev_stage[i]);
   delete c;
 }
 
@@ -540,6 +566,7 @@ int trk_event(trk_ctx* c, const float* d_x, int64_t n, int32_t* d_labels, trk_ev
     info->n_filt_edges = n_filt;
     info->n_kept_edges = (uint32_t)c->host_words[2];
     info->n_saturated = c->host_words[17];
+    read_stage_times(c, info->stage_ms);
   }
   if (n_cand > c->cfg.max_cand_edges || n_filt > c->cfg.max_kept_edges) return TRK_E_CAPACITY;
   if (c->host_words[0] & TRK_ERRBIT_INDEX) return TRK_E_DEVICE;
@@ -634,6 +661,7 @@ extern "C" int trk_batch(trk_ctx* c, int32_t n_events, const float* d_x, const i
       infos[b].n_filt_edges = counts[b * 4 + 1];
       infos[b].n_kept_edges = counts[b * 4 + 2];
       infos[b].n_saturated = counts[b * 4 + 3];
+      read_stage_times(c, infos[b].stage_ms);
     }
   if (n_cand > c->cfg.max_cand_edges || n_filt > c->cfg.max_kept_edges) return TRK_E_CAPACITY;
   if (c->host_words[0] & TRK_ERRBIT_INDEX) return TRK_E_DEVICE;

@@ -37,16 +37,21 @@ class trk_config(ctypes.Structure):
                 ("filter_cut", ctypes.c_float), ("score_cut", ctypes.c_float),
                 ("precision", ctypes.c_int32),
                 ("max_hits", ctypes.c_int64), ("max_cand_edges", ctypes.c_int64),
-                ("max_kept_edges", ctypes.c_int64), ("max_events", ctypes.c_int32)]
+                ("max_kept_edges", ctypes.c_int64), ("max_events", ctypes.c_int32),
+                ("stage_timing", ctypes.c_int32)]
 
 
 class trk_event_info(ctypes.Structure):
     _fields_ = [("n_hits", ctypes.c_int64), ("n_cand_edges", ctypes.c_int64),
                 ("n_filt_edges", ctypes.c_int64), ("n_kept_edges", ctypes.c_int64),
-                ("n_saturated", ctypes.c_int64)]
+                ("n_saturated", ctypes.c_int64), ("stage_ms", ctypes.c_float * 8)]
+
+    STAGES = ("embed", "graph", "filter", "filter_cut", "gnn", "components")
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        d = {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "stage_ms"}
+        d["stage_ms"] = {name: float(self.stage_ms[i]) for i, name in enumerate(self.STAGES)}
+        return d
 
 
 _lib = None
@@ -103,7 +108,8 @@ def _stream(stream=None):
 # ---------------------------------------------------------------------------
 # configuration and weights
 # ---------------------------------------------------------------------------
-def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max_kept_edges=None, max_events=1):
+def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max_kept_edges=None, max_events=1,
+                stage_timing=False):
     """trk_config from an object with the network and pipeline attributes
     (emb_hidden, emb_layers, emb_dim, filt_hidden, filt_layers, gnn_hidden,
     gnn_iters, radius, k_max, filter_cut, score_cut)."""
@@ -115,7 +121,7 @@ def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max
     return trk_config(TRK_ABI_VERSION, cfg.emb_hidden, cfg.emb_layers, cfg.emb_dim, cfg.filt_hidden,
                       cfg.filt_layers, cfg.gnn_hidden, cfg.gnn_iters, float(cfg.radius), cfg.k_max,
                       float(cfg.filter_cut), float(cfg.score_cut), int(precision), max_hits, cand, kept,
-                      int(max_events))
+                      int(max_events), int(bool(stage_timing)))
 
 
 NET_ORDER = ("emb", "filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
@@ -210,10 +216,11 @@ class Pipeline:
     """A context plus allocation of outputs; each method returns torch tensors."""
 
     def __init__(self, cfg, nets, precision="fp32", device=0, max_hits=None, max_cand_edges=None,
-                 max_kept_edges=None, max_events=1):
+                 max_kept_edges=None, max_events=1, stage_timing=False):
         self.cfg = cfg
         self.device = torch.device("cuda", device)
-        self.config = make_config(cfg, precision, max_hits, max_cand_edges, max_kept_edges, max_events)
+        self.config = make_config(cfg, precision, max_hits, max_cand_edges, max_kept_edges, max_events,
+                                  stage_timing)
         self.ctx = trk_create(self.config, pack_weights(cfg, nets), device)
 
     def close(self):
