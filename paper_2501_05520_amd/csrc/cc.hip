@@ -14,10 +14,13 @@
 
 namespace {
 
+// Plain loads suffice: a parent value only ever moves to an ancestor, so a stale
+// cached value is still an ancestor and the walk still ends at a root (if that
+// root is stale, the compare-and-swap below fails and returns the current value).
 __device__ __forceinline__ int uf_find(int* parent, int x) {
-  int p = load_relaxed(&parent[x]);
+  int p = parent[x];
   while (p != x) {
-    const int gp = load_relaxed(&parent[p]);
+    const int gp = parent[p];
     if (gp != p) parent[x] = gp;  // path halving: gp is an ancestor of x
     x = p;
     p = gp;
@@ -66,11 +69,13 @@ __global__ void uf_hook(int* parent, const int* __restrict__ src, const int* __r
 
 __global__ void uf_compress(int* parent, int n) {
   GRID_STRIDE(i, n) {
+    // all links were made by the previous kernel, so every value read here is an
+    // ancestor and the walk ends at the final root
     int x = (int)i;
-    int p = load_relaxed(&parent[x]);
+    int p = parent[x];
     while (p != x) {
       x = p;
-      p = load_relaxed(&parent[x]);
+      p = parent[x];
     }
     parent[i] = x;
   }

@@ -174,6 +174,8 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
 // ---------------------------------------------------------------------------
 // edge step: e <- e + tanh(tanh(e W_c + b1 + P_a[s] + P_b[t]) W2 + b2)
 // edge output (OUT = true): p = sigmoid(tanh(e W_c + b1 + Q_a[s] + Q_b[t]) . w2 + b2)
+// The gathered projections are summed into an FP32 LDS tile with coalesced row
+// loads before the product; the hidden activation t1 reuses that tile.
 // ---------------------------------------------------------------------------
 template <class P, int H, int MT, int NW, bool OUT>
 __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __restrict__ e,
@@ -183,10 +185,14 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
                                                        DevVec lo, float* __restrict__ scores) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
+  constexpr int LDP = H + 4;                       // fp32 row stride of the gathered tile
+  constexpr int V = 16 / (int)sizeof(T);           // act elements per 16-byte chunk
   __shared__ __align__(16) T et[MT * S::LDH];
-  __shared__ __align__(16) T t1[OUT ? 16 : MT * S::LDH];
+  __shared__ __align__(16) float pre[MT * LDP];
+  static_assert(MT * S::LDH * (int)sizeof(T) <= MT * LDP * 4, "t1 must fit in the gathered tile");
   __shared__ float zred[NW * MT];
   __shared__ int sidx[MT], didx[MT];
+  T* t1 = (T*)pre;
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
   const int64_t ntiles = (m + MT - 1) / MT;
@@ -205,6 +211,17 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
       didx[mm] = b;
     }
     __syncthreads();
+    // pre[m][c] = proj[src_m][c] + proj[dst_m][H + c] + b1[c]
+    for (int idx = threadIdx.x; idx < MT * (H / V); idx += blockDim.x) {
+      const int mm = idx / (H / V), c = (idx - mm * (H / V)) * V;
+      const uint4 ua = *(const uint4*)(proj + (size_t)sidx[mm] * 2 * H + c);
+      const uint4 ub = *(const uint4*)(proj + (size_t)didx[mm] * 2 * H + H + c);
+      const T* pa = (const T*)&ua;
+      const T* pb = (const T*)&ub;
+#pragma unroll
+      for (int q = 0; q < V; ++q) pre[mm * LDP + c + q] = (float)pa[q] + (float)pb[q] + lc.b[c + q];
+    }
+    __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, et, S::LDH, lc.w, lc.nkb, wave * S::NTW, 0, lc.nkb);
@@ -214,23 +231,18 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = *(const float4*)(lc.b + nn);
       float4 w2 = make_float4(0.f, 0.f, 0.f, 0.f);
       if (OUT) w2 = *(const float4*)(lo.w + nn);
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int mm = i * 16 + r;
-        float pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
-        load4<P>(proj + (size_t)sidx[mm] * 2 * H + nn, pa0, pa1, pa2, pa3);
-        load4<P>(proj + (size_t)didx[mm] * 2 * H + H + nn, pb0, pb1, pb2, pb3);
-        const float v0 = trk_tanh(acc[i][j][0] + b.x + pa0 + pb0);
-        const float v1 = trk_tanh(acc[i][j][1] + b.y + pa1 + pb1);
-        const float v2 = trk_tanh(acc[i][j][2] + b.z + pa2 + pb2);
-        const float v3 = trk_tanh(acc[i][j][3] + b.w + pa3 + pb3);
-        if (OUT)
-          part[i] += v0 * w2.x + v1 * w2.y + v2 * w2.z + v3 * w2.w;
-        else
-          P::store4(t1 + mm * S::LDH + nn, v0, v1, v2, v3);
+        const float4 pv = *(const float4*)(pre + mm * LDP + nn);
+        const float v0 = trk_tanh(acc[i][j][0] + pv.x);
+        const float v1 = trk_tanh(acc[i][j][1] + pv.y);
+        const float v2 = trk_tanh(acc[i][j][2] + pv.z);
+        const float v3 = trk_tanh(acc[i][j][3] + pv.w);
+        if (OUT) part[i] += v0 * w2.x + v1 * w2.y + v2 * w2.z + v3 * w2.w;
+        acc[i][j] = f32x4{v0, v1, v2, v3};
       }
     }
     if (OUT) {
@@ -248,6 +260,14 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
       }
       __syncthreads();
     } else {
+      __syncthreads();                 // every lane has read its part of pre
+#pragma unroll
+      for (int j = 0; j < S::NTW; ++j) {
+        const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+#pragma unroll
+        for (int i = 0; i < S::MTW; ++i)
+          P::store4(t1 + (i * 16 + r) * S::LDH + nn, acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+      }
       __syncthreads();
       acc_zero(acc);
       tile_gemm<P, S::MTW, S::NTW>(acc, t1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
@@ -272,67 +292,75 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// node step: m_i = sum of incident edge states (CSR by src, then CSC by dst, each in
-// ascending edge order); h <- h + tanh(tanh([h, m] W1 + b1) W2 + b2);
-// proj = h [W_a | W_b] for the next edge step (or the output head)
+// aggregation: msg[i] = sum of the states of i's incident edges, the CSR (by
+// source) list then the CSC (by destination) list, each in ascending edge order.
+// A wave serves one node; its lanes form RPS groups that each read one edge row
+// per step (16 bytes per lane), and the groups' partial sums are combined in a
+// fixed order, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <class P, int H>
+__global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t* __restrict__ e,
+                                                        const int* __restrict__ sptr, const int* __restrict__ sidx,
+                                                        const int* __restrict__ dptr, const int* __restrict__ didx,
+                                                        int n, float* __restrict__ msg) {
+  typedef typename P::act_t T;
+  constexpr int V = 16 / (int)sizeof(T);   // columns per lane per row
+  constexpr int LPR = H / V;               // lanes per row
+  constexpr int RPS = 64 / LPR;            // rows per wave step
+  static_assert(LPR >= 1 && LPR <= 64 && 64 % LPR == 0, "row split");
+  const int l = lane_id();
+  const int grp = l / LPR, col = (l % LPR) * V;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  for (int node = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); node < n; node += waves) {
+    float acc[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) acc[q] = 0.f;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int* ptr = pass == 0 ? sptr : dptr;
+      const int* idx = pass == 0 ? sidx : didx;
+      const int b = ptr[node], end = ptr[node + 1];
+      for (int k = b + grp; k < end; k += RPS) {
+        const uint4 u = *(const uint4*)(e + (size_t)idx[k] * H + col);
+        const T* v = (const T*)&u;
+#pragma unroll
+        for (int q = 0; q < V; ++q) acc[q] += (float)v[q];
+      }
+    }
+    // combine the row groups: lanes with the same column, fixed butterfly order
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+      for (int q = 0; q < V; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
+    if (grp == 0) {
+#pragma unroll
+      for (int q = 0; q < V; q += 4)
+        *(float4*)(msg + (size_t)node * H + col + q) = make_float4(acc[q], acc[q + 1], acc[q + 2], acc[q + 3]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node step: h <- h + tanh(tanh([h, m] W1 + b1) W2 + b2) with m the aggregated
+// messages; proj = h [W_a | W_b] for the next edge step (or the output head)
 // ---------------------------------------------------------------------------
 template <class P, int H, int MT, int NW>
-__global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ h, const typename P::act_t* __restrict__ e,
-                                                            const int* __restrict__ sptr, const int* __restrict__ sidx,
-                                                            const int* __restrict__ dptr, const int* __restrict__ didx,
+__global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ h, const float* __restrict__ msg,
                                                             int n, DevLayer l1, DevLayer l2, DevLayer lp,
                                                             typename P::act_t* __restrict__ proj) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
-  constexpr int CPL = (H + 63) / 64;  // columns per lane in the aggregation
   __shared__ __align__(16) T in[MT * S::LD2];
   __shared__ __align__(16) T t1[MT * S::LDH];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int ntiles = (n + MT - 1) / MT;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int row0 = t * MT;
-    // aggregation and staging of [h, m]; one wave per node
-    for (int mm = wave; mm < MT; mm += NW) {
+    // staging of [h, m] as the working precision
+    for (int idx = threadIdx.x; idx < MT * H; idx += blockDim.x) {
+      const int mm = idx / H, col = idx - mm * H;
       const int node = row0 + mm;
-      float acc[CPL];
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) acc[c] = 0.f;
-      if (node < n) {
-        for (int pass = 0; pass < 2; ++pass) {
-          const int* ptr = pass == 0 ? sptr : dptr;
-          const int* idx = pass == 0 ? sidx : didx;
-          const int b = ptr[node], end = ptr[node + 1];
-          int k = b;
-          for (; k + 4 <= end; k += 4) {
-            const int e0 = idx[k], e1 = idx[k + 1], e2 = idx[k + 2], e3 = idx[k + 3];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-              const int col = l + 64 * c;
-              if (col < H) {
-                const float v0 = (float)e[(size_t)e0 * H + col], v1 = (float)e[(size_t)e1 * H + col];
-                const float v2 = (float)e[(size_t)e2 * H + col], v3 = (float)e[(size_t)e3 * H + col];
-                acc[c] = (((acc[c] + v0) + v1) + v2) + v3;
-              }
-            }
-          }
-          for (; k < end; ++k) {
-            const int e0 = idx[k];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-              const int col = l + 64 * c;
-              if (col < H) acc[c] += (float)e[(size_t)e0 * H + col];
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int col = l + 64 * c;
-        if (col < H) {
-          in[mm * S::LD2 + H + col] = P::cvt(acc[c]);
-          in[mm * S::LD2 + col] = P::cvt(node < n ? h[(size_t)node * H + col] : 0.f);
-        }
-      }
+      in[mm * S::LD2 + col] = P::cvt(node < n ? h[(size_t)node * H + col] : 0.f);
+      in[mm * S::LD2 + H + col] = P::cvt(node < n ? msg[(size_t)node * H + col] : 0.f);
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
@@ -432,9 +460,9 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
       edge_kernel<P, H, MT, NW, false><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
                                                                  net.edge_2, net.out_2, nullptr);
     const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
+    aggregate_kernel<P, H><<<blocks_for(n, 4, 16384), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
     if (ngrid > 0)
-      node_step_kernel<P, H, MT, NW><<<ngrid, NW * 64, 0, s>>>(g.h, e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n,
-                                                               net.node_1, net.node_2, lp, proj);
+      node_step_kernel<P, H, MT, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
   }
   if (egrid > 0)
     edge_kernel<P, H, MT, NW, true><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,

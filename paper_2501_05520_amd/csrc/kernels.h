@@ -78,6 +78,7 @@ void launch_components(int n, const int* src, const int* dst, const float* score
 // ---- gnn.hip ----
 struct GnnScratch {
   float* h = nullptr;        // [n][H] node state fp32
+  float* msg = nullptr;      // [n][H] aggregated messages fp32
   void* proj = nullptr;      // [n][2H] act type: per-node projections [h W1a | h W1b]
   void* e = nullptr;         // [cap][H] act type: edge state
   int* rowptr = nullptr;     // [n+1] CSR by src

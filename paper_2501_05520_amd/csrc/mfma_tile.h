@@ -78,6 +78,9 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
   for (int j = 0; j < NTW; ++j) w[j] = wl[((size_t)j * nkb + kb0) * 64];
   for (int kk = 0; kk < nkb_run; ++kk) {
     const int kb = kb0 + kk;
+    // the last block re-reads itself so that every load is unconditional and the
+    // compiler can wait for each fragment individually
+    const int kbn = kk + 1 < nkb_run ? kb + 1 : kb;
     uint4 xf[MTW];
 #pragma unroll
     for (int i = 0; i < MTW; ++i) xf[i] = *(const uint4*)(xl + i * 16 * ldx + kb * P::KB);
@@ -85,7 +88,9 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
     for (int j = 0; j < NTW; ++j) {
 #pragma unroll
       for (int i = 0; i < MTW; ++i) P::mma(acc[i][j], w[j], xf[i]);
-      if (kk + 1 < nkb_run) w[j] = wl[((size_t)j * nkb + kb + 1) * 64];
+      w[j] = wl[((size_t)j * nkb + kbn) * 64];
+      // keep the issue order: n-tile j's products, then its next fragment request
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }

@@ -331,6 +331,7 @@ int alloc_scratch(trk_ctx* c) {
   a.add(g.counters, 8);
   a.add(g.tmp, tmp_ints);
   a.add(s.h, (size_t)NH * H);
+  a.add(s.msg, (size_t)NH * H);
   a.add_bytes(s.proj, (size_t)NH * 2 * H * act);
   a.add_bytes(s.e, (size_t)CF * H * act);
   a.add(s.rowptr, NH + 1);

@@ -1,0 +1,201 @@
+"""GPU parity with the full-size network (embedding 3->3x1024->12, filter
+24->3x512->1, interaction network H=128, T=8, radius 0.2, K=256), in the launch
+configuration the benchmark times:
+  * a pile-up-10 event (5,500 hits), small enough for the whole FP64 oracle:
+    every stage stage-isolated and the chain end to end;
+  * the pile-up-200 event (110,000 hits): embedding on sampled hits, the radius
+    graph in full, filter scores on sampled edges, components in full, the
+    interaction network in full with one iteration, batch-vs-alone identity.
+BF16 runs report their error against the oracle and assert only sanity bounds."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gen import MU200, make_weights, generate_event, pack_events
+from tests.gpu_helpers import compare_edges, label_agreement
+
+pytestmark = pytest.mark.gpu
+
+SCORE_TOL = 1e-4
+EMB_TOL = 1e-5   # relative to max(1, |emb|)
+MID_SEED, FULL_SEED = 300, 200
+
+
+@pytest.fixture(scope="module")
+def nets():
+    return make_weights(MU200, 0)
+
+
+@pytest.fixture(scope="module")
+def pipe(nets):
+    from paper_2501_05520_amd.trk import Pipeline
+    p = Pipeline(MU200, nets, "fp32", max_hits=2 * 110000 + 64, max_events=4)
+    yield p
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def mid(nets):
+    ev = generate_event(MID_SEED, 10)
+    return ev, oracle.event(ev.x, nets, MU200)
+
+
+@pytest.fixture(scope="module")
+def full(nets):
+    ev = generate_event(FULL_SEED, MU200.n_collisions)
+    emb = oracle.embed(ev.x, nets)
+    return ev, emb
+
+
+# ---------------------------------------------------------------- mid-size event
+def test_mid_embed(pipe, mid):
+    ev, r = mid
+    emb = pipe.embed(ev.x).cpu().numpy()
+    err = np.abs(emb - r["emb"]) / np.maximum(1.0, np.abs(r["emb"]))
+    assert err.max() <= EMB_TOL, err.max()
+
+
+def test_mid_graph(pipe, mid):
+    ev, r = mid
+    e32 = r["emb"].astype(np.float32)
+    src, dst, _ = pipe.build_graph(e32)
+    rad = float(np.float32(MU200.radius))
+    lo, hi, d2 = oracle.radius_pairs(e32, rad)
+    os_, od, _ = oracle.radius_graph(e32, rad, MU200.k_max)
+    _, nbad, det = compare_edges(e32, src.cpu().numpy(), dst.cpu().numpy(), os_, od, rad, MU200.k_max, lo, hi, d2)
+    assert nbad == 0, det
+
+
+def test_mid_filter_and_gnn(pipe, mid, nets):
+    ev, r = mid
+    e32 = r["emb"].astype(np.float32)
+    p, _, _ = pipe.filter(e32, r["src"], r["dst"])
+    p_ref = oracle.filter_scores(e32, r["src"], r["dst"], nets)
+    assert np.abs(p.cpu().numpy() - p_ref).max() <= SCORE_TOL
+    q = pipe.gnn(ev.x, r["fsrc"], r["fdst"]).cpu().numpy()
+    assert np.abs(q - r["gnn_scores"]).max() <= SCORE_TOL
+
+
+def test_mid_end_to_end(pipe, mid):
+    ev, r = mid
+    labels, info = pipe.event(ev.x)
+    labels = labels.cpu().numpy()
+    margin = int(np.sum(np.abs(r["filter_scores"] - MU200.filter_cut) <= SCORE_TOL)) + \
+        int(np.sum(np.abs(r["gnn_scores"] - MU200.score_cut) <= SCORE_TOL))
+    print(f"mid event: n={ev.n} E_c={info['n_cand_edges']} E_f={info['n_filt_edges']} margin={margin}")
+    assert abs(info["n_cand_edges"] - r["src"].size) <= 2
+    if margin == 0 and info["n_cand_edges"] == r["src"].size:
+        assert np.array_equal(labels, r["labels"])
+    else:
+        hit, jac = label_agreement(labels, r["labels"])
+        assert hit >= 0.99
+
+
+# ---------------------------------------------------------------- pile-up 200
+def test_full_embed_sampled(pipe, full, nets):
+    ev, emb_ref = full
+    emb = pipe.embed(ev.x).cpu().numpy()
+    assert emb.shape == (110000, 12)
+    err = np.abs(emb - emb_ref) / np.maximum(1.0, np.abs(emb_ref))
+    assert err.max() <= EMB_TOL, err.max()
+
+
+@pytest.fixture(scope="module")
+def full_graph(pipe, full):
+    ev, emb_ref = full
+    e32 = emb_ref.astype(np.float32)
+    src, dst, nsat = pipe.build_graph(e32)
+    rad = float(np.float32(MU200.radius))
+    lo, hi, d2 = oracle.radius_pairs(e32, rad)
+    os_, od, cnt = oracle.radius_graph(e32, rad, MU200.k_max)
+    return e32, src.cpu().numpy(), dst.cpu().numpy(), nsat, (lo, hi, d2), (os_, od, cnt)
+
+
+def test_full_graph(full_graph):
+    e32, src, dst, nsat, (lo, hi, d2), (os_, od, cnt) = full_graph
+    assert 2_000_000 <= src.size <= 5_000_000
+    assert np.all(src < dst) and np.all(np.diff(src.astype(np.int64) * 110000 + dst) > 0)
+    ndiff, nbad, det = compare_edges(e32, src, dst, os_, od, float(np.float32(MU200.radius)), MU200.k_max,
+                                     lo, hi, d2)
+    print(f"mu200 graph: E_c={src.size} oracle={os_.size} in-band differences={ndiff} saturated={nsat}")
+    assert nbad == 0, det
+    assert nsat > 0
+
+
+def test_full_filter_sampled(pipe, full_graph, nets):
+    e32, _, _, _, _, (os_, od, _) = full_graph
+    p, ks, kd = pipe.filter(e32, os_, od)
+    p = p.cpu().numpy()
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(os_.size, 20000, replace=False))
+    p_ref = oracle.filter_scores(e32, os_[idx], od[idx], nets)
+    assert np.abs(p[idx] - p_ref).max() <= SCORE_TOL
+    keep = p > np.float32(MU200.filter_cut)
+    assert ks.numel() == int(keep.sum())
+    assert 500_000 <= ks.numel() <= 2_000_000
+
+
+def test_full_gnn_one_iteration(full_graph, nets, full):
+    """The interaction-network kernels at full size (1M edges), one message-passing step."""
+    from paper_2501_05520_amd.trk import Pipeline
+    ev, _ = full
+    e32, _, _, _, _, (os_, od, _) = full_graph
+    cfg1 = MU200.with_(gnn_iters=1)
+    nets1 = make_weights(cfg1, 0)
+    p1 = Pipeline(cfg1, nets1, "fp32", max_hits=110000, max_cand_edges=4_000_000, max_kept_edges=4_000_000)
+    fs, fd = os_[::3], od[::3]     # a ~1M-edge subset as the GNN input
+    q = p1.gnn(ev.x, fs, fd).cpu().numpy()
+    q_ref = oracle.interaction_network(ev.x, fs, fd, nets1, 1)
+    p1.close()
+    assert fs.size > 900_000
+    assert np.abs(q - q_ref).max() <= SCORE_TOL
+
+
+def test_full_components(pipe, full_graph):
+    _, src, dst, _, _, _ = full_graph
+    rng = np.random.default_rng(3)
+    sc = rng.uniform(0, 1, src.size).astype(np.float32)
+    got = pipe.components(110000, src, dst, sc, 0.5).cpu().numpy()
+    want = oracle.components(110000, src, dst, sc, np.float32(0.5))
+    assert np.array_equal(got, want)
+
+
+def test_full_batch_equals_alone(pipe, full):
+    ev1, _ = full
+    ev2 = generate_event(FULL_SEED + 1, MU200.n_collisions)
+    x, offs = pack_events([ev1, ev2])
+    labels, infos = pipe.batch(x, offs)
+    labels = labels.cpu().numpy()
+    for b, ev in enumerate([ev1, ev2]):
+        alone, info = pipe.event(ev.x)
+        assert np.array_equal(labels[offs[b]:offs[b + 1]], alone.cpu().numpy())
+        assert infos[b]["n_cand_edges"] == info["n_cand_edges"]
+        assert infos[b]["n_kept_edges"] == info["n_kept_edges"]
+
+
+def test_full_deterministic(pipe, full):
+    ev, _ = full
+    a, ia = pipe.event(ev.x)
+    b, ib = pipe.event(ev.x)
+    assert torch.equal(a, b) and ia == ib
+
+
+# ---------------------------------------------------------------- BF16 (reported)
+def test_bf16_error_report(nets, mid):
+    from paper_2501_05520_amd.trk import Pipeline
+    ev, r = mid
+    pb = Pipeline(MU200, nets, "bf16", max_hits=8192)
+    e32 = r["emb"].astype(np.float32)
+    emb = pb.embed(ev.x).cpu().numpy()
+    pf = pb.filter(e32, r["src"], r["dst"])[0].cpu().numpy()
+    q = pb.gnn(ev.x, r["fsrc"], r["fdst"]).cpu().numpy()
+    labels, _ = pb.event(ev.x)
+    pb.close()
+    de = np.abs(emb - r["emb"]).max()
+    dpf = np.abs(pf - r["filter_scores"])
+    dq = np.abs(q - r["gnn_scores"])
+    hit, jac = label_agreement(labels.cpu().numpy(), r["labels"])
+    print(f"bf16 vs fp64 oracle: emb max {de:.3g}; filter |dp| max {dpf.max():.3g} p99 {np.percentile(dpf, 99):.3g}; "
+          f"gnn |dp| max {dq.max():.3g} p99 {np.percentile(dq, 99):.3g}; hit agreement {hit:.4f} jaccard {jac:.4f}")
+    assert dpf.max() < 0.1 and dq.max() < 0.2
