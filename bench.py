@@ -35,6 +35,7 @@ def parse():
     p.add_argument("--no-variant", action="store_true", help="skip the BF16 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
+    p.add_argument("--serve-seconds", type=float, default=6.0, help="0 skips the serving measurement")
     return p.parse_args()
 
 
@@ -79,6 +80,77 @@ def agreement(la, lb, min_hits=3):
     ca, cb = cands(la), cands(lb)
     u = ca | cb
     return hit, (len(ca & cb) / len(u) if u else 1.0)
+
+
+def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed=7, pool=6):
+    """Serving mix: client threads with Poisson arrivals submit events whose
+    pile-up is drawn uniformly from {50, 100, 140, 200}; one collector harvests
+    results.  First a burst measures the saturated rate, then the offered load is
+    load_frac x that rate for `seconds`.  Latency = submission -> labels on host."""
+    import queue
+    import random
+    import threading
+    from gen import SERVE_MUS, generate_event
+    pools = {mu: [generate_event(9000 + 97 * mu + k, mu).x for k in range(pool)] for mu in SERVE_MUS}
+    srv = trk.Server(cfg, nets, precision, n_slots=3, max_batch_events=8, max_batch_hits=330000,
+                     mem_budget_bytes=64 << 30)
+    # warm-up and saturated rate: a burst of 48 requests
+    burst = [pools[SERVE_MUS[k % 4]][k % pool] for k in range(48)]
+    t0 = time.perf_counter()
+    tickets = [(srv.submit(x), x.shape[0]) for x in burst]
+    for t, n in tickets:
+        srv.wait(t, n)
+    sat = len(burst) / (time.perf_counter() - t0)
+    rate = load_frac * sat
+    done = queue.Queue()
+    lat, status = [], []
+    stop_at = time.perf_counter() + seconds
+
+    def client(c):
+        rng = random.Random(seed * 1000 + c)
+        nxt = time.perf_counter()
+        while True:
+            nxt += rng.expovariate(rate / n_clients)
+            if nxt > stop_at:
+                break
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            x = pools[rng.choice(SERVE_MUS)][rng.randrange(pool)]
+            done.put((srv.submit(x), x.shape[0]))
+        done.put(None)
+
+    def collector():
+        ended = 0
+        while ended < n_clients:
+            item = done.get()
+            if item is None:
+                ended += 1
+                continue
+            rc, _, _, ms = srv.wait(*item)
+            status.append(rc)
+            lat.append(ms)
+
+    st0 = srv.stats()
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]
+    col = threading.Thread(target=collector)
+    t1 = time.perf_counter()
+    for t in threads + [col]:
+        t.start()
+    for t in threads + [col]:
+        t.join()
+    wall = time.perf_counter() - t1
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    nb = st["batches"] - st0["batches"]
+    return {"precision": precision, "saturated_events_per_s": round(sat, 2), "offered_events_per_s": round(rate, 2),
+            "achieved_events_per_s": round(len(lat) / wall, 2), "requests": int(len(lat)),
+            "errors": int(sum(1 for r in status if r != 0)),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2)},
+            "mean_batch_events": round((st["batched_events"] - st0["batched_events"]) / max(nb, 1), 2),
+            "waited_for_memory": st["waited_for_memory"] - st0["waited_for_memory"],
+            "slots": 3, "clients": n_clients, "mix_mu": list(SERVE_MUS)}
 
 
 def cpu_baseline(cfg, nets, x):
@@ -181,6 +253,8 @@ def main():
             "candidate_jaccard_vs_primary": round(float(np.mean([a[1] for a in agr])), 5),
             "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
         }
+    if args.serve_seconds > 0:
+        result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, nets, xs[0])
     print(json.dumps(result), flush=True)

@@ -50,6 +50,8 @@ typedef enum {
   TRK_E_CAPACITY = -3,  /* an edge count exceeds the capacity given */
   TRK_E_DEVICE = -4,    /* a HIP runtime call failed */
   TRK_E_WEIGHTS = -5,   /* weight blob malformed or inconsistent with the configuration */
+  TRK_E_EXPIRED = -7,   /* a served request's deadline passed before it was run */
+  TRK_E_SHUTDOWN = -8,  /* the server is shutting down */
 } trk_status;
 
 typedef enum {
@@ -164,6 +166,62 @@ int trk_event(trk_ctx* ctx, const float* d_x, int64_t n, int32_t* d_labels, trk_
  * event.  Synchronises like trk_event. */
 int trk_batch(trk_ctx* ctx, int32_t n_events, const float* d_x, const int64_t* h_offsets,
               int32_t* d_labels, trk_event_info* infos, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Serving loop: the analogue of the inference server of Section 2.3 (clients
+ * send requests, the server batches them and runs them on its GPU) and of the
+ * concurrent model instances of Section 4.2.1, in process.  Client threads submit
+ * events (host memory); a request is admitted once the memory estimate of all
+ * admitted, unfinished requests fits mem_budget_bytes (submission blocks until
+ * then; a request whose estimate alone exceeds the budget is refused with
+ * TRK_E_CAPACITY).  n_slots workers each own a context, a stream and staging
+ * buffers; a free worker takes the queued requests in arrival order, up to
+ * max_batch_events events and max_batch_hits spacepoints, and runs them as one
+ * trk_batch, so requests arriving while batches run join the next batch and work of
+ * different batches overlaps on the device.  Labels equal those of trk_event on
+ * each event alone.  All server calls are thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct trk_server trk_server;
+
+typedef struct {
+  int32_t n_slots;            /* concurrent batches, 1..16 */
+  int32_t max_batch_events;   /* events per batch, 1..65535 */
+  int64_t max_batch_hits;     /* spacepoints per batch (also the largest single request) */
+  int64_t max_cand_edges;     /* per-slot capacities (0: max_batch_hits * k_max) */
+  int64_t max_kept_edges;     /* (0: same as max_cand_edges) */
+  uint64_t mem_budget_bytes;  /* admission budget over admitted, unfinished requests */
+  uint64_t bytes_per_hit;     /* admission estimate per spacepoint (0: slot memory / max_batch_hits) */
+} trk_server_config;
+
+typedef struct {
+  int64_t submitted, completed, rejected, expired, batches, batched_events;
+  int64_t admitted_at_once, waited_for_memory;
+  uint64_t inflight_bytes, peak_inflight_bytes;
+  uint64_t slot_bytes;        /* device memory of one slot (context arena + weights + staging) */
+} trk_server_info;
+
+/* Creates a server with n_slots contexts on device_id; cfg's max_hits,
+ * max_events and capacities are taken from scfg.  Errors as trk_create. */
+int trk_server_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int device_id,
+                      const trk_server_config* scfg, trk_server** out);
+
+/* Copies h_x[n][3] and enqueues it; *ticket identifies the request.  Blocks while
+ * the budget is full.  deadline_ms > 0: the request expires (TRK_E_EXPIRED at
+ * trk_server_wait) if not batched within that time.  n > max_batch_hits:
+ * TRK_E_CAPACITY. */
+int trk_server_submit(trk_server* srv, const float* h_x, int64_t n, double deadline_ms, int64_t* ticket);
+
+/* Waits for a request and releases its ticket: writes h_labels[n] (host), the
+ * counts and stage times (info, optional) and the latency from submission to
+ * completion in ms (optional); returns the request's status. */
+int trk_server_wait(trk_server* srv, int64_t ticket, int32_t* h_labels, trk_event_info* info,
+                    double* latency_ms);
+
+int trk_server_stats(trk_server* srv, trk_server_info* out);
+
+/* Drains (runs every admitted request), stops the workers and frees the slots;
+ * tickets not yet waited for are released. */
+void trk_server_destroy(trk_server* srv);
 
 /* Static description of a status code. */
 const char* trk_strerror(int status);

@@ -17,9 +17,11 @@ TRK_ABI_VERSION = 1
 TRK_WEIGHTS_MAGIC = 0x5754524B
 TRK_FP32, TRK_BF16 = 0, 1
 STATUS = {0: "TRK_OK", -1: "TRK_E_INVAL", -2: "TRK_E_NOMEM", -3: "TRK_E_CAPACITY",
-          -4: "TRK_E_DEVICE", -5: "TRK_E_WEIGHTS"}
+          -4: "TRK_E_DEVICE", -5: "TRK_E_WEIGHTS", -7: "TRK_E_EXPIRED", -8: "TRK_E_SHUTDOWN"}
 EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_filter", "trk_gnn",
-           "trk_components", "trk_event", "trk_batch", "trk_strerror")
+           "trk_components", "trk_event", "trk_batch", "trk_strerror",
+           "trk_server_create", "trk_server_submit", "trk_server_wait", "trk_server_stats",
+           "trk_server_destroy")
 
 
 class TrkError(RuntimeError):
@@ -54,6 +56,22 @@ class trk_event_info(ctypes.Structure):
         return d
 
 
+class trk_server_config(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("max_batch_events", ctypes.c_int32),
+                ("max_batch_hits", ctypes.c_int64), ("max_cand_edges", ctypes.c_int64),
+                ("max_kept_edges", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_uint64),
+                ("bytes_per_hit", ctypes.c_uint64)]
+
+
+class trk_server_info(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "expired", "batches",
+                                              "batched_events", "admitted_at_once", "waited_for_memory")] + \
+               [(k, ctypes.c_uint64) for k in ("inflight_bytes", "peak_inflight_bytes", "slot_bytes")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -76,10 +94,17 @@ def lib():
         L.trk_components.argtypes = [P, I64, P, P, P, I64, F, P, P]
         L.trk_event.argtypes = [P, P, I64, P, ctypes.POINTER(trk_event_info), P]
         L.trk_batch.argtypes = [P, I32, P, P, P, ctypes.POINTER(trk_event_info), P]
+        L.trk_server_create.argtypes = [ctypes.POINTER(trk_config), P, ctypes.c_size_t, ctypes.c_int,
+                                        ctypes.POINTER(trk_server_config), ctypes.POINTER(P)]
+        L.trk_server_submit.argtypes = [P, P, I64, ctypes.c_double, ctypes.POINTER(I64)]
+        L.trk_server_wait.argtypes = [P, I64, P, ctypes.POINTER(trk_event_info), ctypes.POINTER(ctypes.c_double)]
+        L.trk_server_stats.argtypes = [P, ctypes.POINTER(trk_server_info)]
+        L.trk_server_destroy.argtypes = [P]
+        L.trk_server_destroy.restype = None
         L.trk_strerror.argtypes = [ctypes.c_int]
         L.trk_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("trk_destroy", "trk_strerror"):
+            if name not in ("trk_destroy", "trk_strerror", "trk_server_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -292,3 +317,77 @@ class Pipeline:
         labels = torch.empty(max(x.shape[0], 1), dtype=torch.int32, device=self.device)[:x.shape[0]]
         infos = trk_batch(self.ctx, x, offsets, labels)
         return labels, infos
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+# ---------------------------------------------------------------------------
+def trk_server_create(config, weights_blob, device, server_config):
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(weights_blob, len(weights_blob))
+    _check(lib().trk_server_create(ctypes.byref(config), buf, len(weights_blob), int(device),
+                                   ctypes.byref(server_config), ctypes.byref(h)), "trk_server_create")
+    return h
+
+
+def trk_server_submit(srv, x, deadline_ms=0.0):
+    """x: host float32 [n, 3]; returns the ticket."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = ctypes.c_int64()
+    _check(lib().trk_server_submit(srv, x.ctypes.data_as(ctypes.c_void_p), x.shape[0], float(deadline_ms),
+                                   ctypes.byref(t)), "trk_server_submit")
+    return t.value
+
+
+def trk_server_wait(srv, ticket, n):
+    """Returns (status, labels int32 [n], info dict, latency ms)."""
+    labels = np.empty(max(int(n), 1), dtype=np.int32)
+    info = trk_event_info()
+    lat = ctypes.c_double()
+    rc = lib().trk_server_wait(srv, int(ticket), labels.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info),
+                               ctypes.byref(lat))
+    return rc, labels[:int(n)], info.as_dict(), lat.value
+
+
+def trk_server_stats(srv):
+    st = trk_server_info()
+    _check(lib().trk_server_stats(srv, ctypes.byref(st)), "trk_server_stats")
+    return st.as_dict()
+
+
+def trk_server_destroy(srv):
+    lib().trk_server_destroy(srv)
+
+
+class Server:
+    """A serving loop on one GPU; submit/wait may be called from many threads."""
+
+    def __init__(self, cfg, nets, precision="bf16", device=0, n_slots=2, max_batch_events=8,
+                 max_batch_hits=220000, mem_budget_bytes=64 << 30, max_cand_edges=0, max_kept_edges=0,
+                 bytes_per_hit=0, stage_timing=False):
+        self.cfg = cfg
+        config = make_config(cfg, precision, max_batch_hits, max_cand_edges or None, max_kept_edges or None,
+                             max_batch_events, stage_timing)
+        scfg = trk_server_config(int(n_slots), int(max_batch_events), int(max_batch_hits), int(max_cand_edges),
+                                 int(max_kept_edges), int(mem_budget_bytes), int(bytes_per_hit))
+        self.h = trk_server_create(config, pack_weights(cfg, nets), device, scfg)
+
+    def submit(self, x, deadline_ms=0.0):
+        return trk_server_submit(self.h, x, deadline_ms)
+
+    def wait(self, ticket, n):
+        return trk_server_wait(self.h, ticket, n)
+
+    def stats(self):
+        return trk_server_stats(self.h)
+
+    def close(self):
+        if self.h is not None:
+            trk_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
