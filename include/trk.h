@@ -84,6 +84,7 @@ typedef struct {
   int64_t max_kept_edges;     /* capacity of filtered edges (GNN input) */
   int32_t max_events;         /* largest batch of trk_batch */
   int32_t stage_timing;       /* non-zero: trk_event / trk_batch time each stage with HIP events */
+  int32_t training;           /* non-zero: allocate the training buffers (FP32 precision only) */
 } trk_config;
 
 /* Per-call counts reported by trk_event / trk_batch (all host memory). */
@@ -222,6 +223,53 @@ int trk_server_stats(trk_server* srv, trk_server_info* out);
 /* Drains (runs every admitted request), stops the workers and frees the slots;
  * tickets not yet waited for are released. */
 void trk_server_destroy(trk_server* srv);
+
+/* ------------------------------------------------------------------------
+ * Training of the filter MLP and the interaction network (FP32 contexts created
+ * with training != 0).  Objective, a reading of the training configuration:
+ * binary cross-entropy with logits on truth labels, averaged over the candidate
+ * edges (filter) and over the filtered edges (interaction network); the edge sets
+ * are inputs held fixed.  Parameters live in one flat FP32 device vector: the
+ * networks filter, node encoder, edge encoder, edge network, node network and
+ * output head, each layer as W[fan_in][fan_out] then b[fan_out] (the weight-blob
+ * order without the embedding).  Gradients use the same layout.  A *_bwd call
+ * uses the state of the preceding *_fwd call of the same context on the same
+ * edges, and adds its gradients to d_grads.  The interaction-network backward
+ * stores only the per-iteration node and edge states in the forward pass and
+ * recomputes each iteration's internals during the backward pass.
+ * ---------------------------------------------------------------------- */
+
+/* Number of floats of the flat parameter (and gradient) vector. */
+int64_t trk_train_param_count(const trk_config* cfg);
+
+/* Loads the flat parameter vector (device) into every kernel layout of the
+ * context, the inference path included; synchronises the stream. */
+int trk_train_set_params(trk_ctx* ctx, const float* d_params, hipStream_t stream);
+
+/* Filter logits z_f[m] of the edges (d_src, d_dst) over d_emb[n][emb_dim], keeping
+ * the activations; m <= max_cand_edges. */
+int trk_filter_train_fwd(trk_ctx* ctx, const float* d_emb, int64_t n, const int32_t* d_src,
+                         const int32_t* d_dst, int64_t m, float* d_logits, hipStream_t stream);
+/* Adds dL/dparams of the filter, given dL/dz_f[m], to d_grads. */
+int trk_filter_train_bwd(trk_ctx* ctx, const float* d_emb, int64_t n, const int32_t* d_src,
+                         const int32_t* d_dst, int64_t m, const float* d_dlogits, float* d_grads,
+                         hipStream_t stream);
+/* Interaction-network logits z_o[m], keeping the per-iteration states; m <= max_kept_edges. */
+int trk_gnn_train_fwd(trk_ctx* ctx, const float* d_x, int64_t n, const int32_t* d_src,
+                      const int32_t* d_dst, int64_t m, float* d_logits, hipStream_t stream);
+/* Adds dL/dparams of the five interaction-network MLPs, given dL/dz_o[m], to d_grads. */
+int trk_gnn_train_bwd(trk_ctx* ctx, const float* d_x, int64_t n, const int32_t* d_src,
+                      const int32_t* d_dst, int64_t m, const float* d_dlogits, float* d_grads,
+                      hipStream_t stream);
+/* Mean binary cross-entropy with logits of z[m] against targets y[m] in {0,1}:
+ * writes dL/dz = (sigmoid(z) - y) / m and, if h_loss, the loss (synchronises). */
+int trk_bce_with_logits(trk_ctx* ctx, const float* d_logits, const float* d_targets, int64_t m,
+                        float* d_dlogits, float* h_loss, hipStream_t stream);
+/* One Adam step (Kingma and Ba) over count parameters with bias correction for
+ * step >= 1; d_m and d_v are the moment vectors (start at zero). */
+int trk_adam_update(trk_ctx* ctx, float* d_params, const float* d_grads, float* d_m, float* d_v,
+                    int64_t count, float lr, float beta1, float beta2, float eps, int64_t step,
+                    hipStream_t stream);
 
 /* Static description of a status code. */
 const char* trk_strerror(int status);

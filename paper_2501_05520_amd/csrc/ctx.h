@@ -1,0 +1,79 @@
+// Internal definition of the context (shared by the C-ABI files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+#include "../../include/trk.h"
+#include "kernels.h"
+
+// ---------------------------------------------------------------------------
+// device arena: one allocation carved into 256-byte aligned pieces
+// ---------------------------------------------------------------------------
+struct Arena {
+  std::vector<std::pair<void**, size_t>> req;
+  void* base = nullptr;
+  size_t total = 0;
+  template <class T>
+  void add(T*& p, size_t count) { req.push_back({(void**)&p, count * sizeof(T)}); }
+  void add_bytes(void*& p, size_t bytes) { req.push_back({&p, bytes}); }
+  hipError_t commit() {
+    total = 0;
+    for (auto& r : req) total += (r.second + 255) & ~(size_t)255;
+    if (total == 0) total = 256;
+    hipError_t e = hipMalloc(&base, total);
+    if (e != hipSuccess) return e;
+    size_t off = 0;
+    for (auto& r : req) {
+      *r.first = (char*)base + off;
+      off += (r.second + 255) & ~(size_t)255;
+    }
+    return hipSuccess;
+  }
+};
+
+
+struct TrainState;
+
+struct trk_ctx {
+  trk_config cfg;
+  int device = 0;
+  int n_cu = 256;
+  int prec = TRK_PREC_F32;
+  hipStream_t own_stream = nullptr;
+  // weights
+  void* wmem = nullptr;
+  DevLayer emb_in, emb_out;
+  LayerList emb_hid;
+  DevLayer filt_in;
+  LayerList filt_hid;
+  DevVec filt_out;
+  DevGNN gnn;
+  // scratch
+  Arena arena;
+  float* emb = nullptr;
+  int* cand_src = nullptr;
+  int* cand_dst = nullptr;
+  float* cand_scores = nullptr;
+  int* filt_src = nullptr;
+  int* filt_dst = nullptr;
+  float* gnn_scores = nullptr;
+  int* ev = nullptr;
+  int64_t* offs = nullptr;
+  int* dev_words = nullptr;  // [16]: 0 err bits, 1 filtered count, 2 kept count, 3.. per-event use
+  int* batch_counts = nullptr;  // [max_events][4] per-event counts
+  GraphScratch graph;
+  GnnScratch gs;
+  int* host_words = nullptr;  // pinned mirror
+  hipEvent_t ev_stage[8] = {};
+  bool timing = false;
+  TrainState* train = nullptr;   // training buffers (trk_config.training != 0)
+};
+
+// training (train.hip)
+int train_create(trk_ctx* c);
+void train_destroy(trk_ctx* c);
+int64_t train_param_count(const trk_config& k);
+int train_set_params(trk_ctx* c, const float* P, hipStream_t s);

@@ -433,19 +433,7 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
   typedef typename P::act_t T;
   T* proj = (T*)g.proj;
   T* e = (T*)g.e;
-  // incidence lists by src and by dst
-  const int* keys[2] = {src, dst};
-  int* ptrs[2] = {g.rowptr, g.cscptr};
-  int* idxs[2] = {g.rowidx, g.cscidx};
-  const int eb = blocks_for(m_cap, 256, 2048);
-  for (int k = 0; k < 2; ++k) {
-    launch_fill_int(g.cnt, 0, n, s);
-    if (m_cap > 0) incidence_count<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, g.cnt);
-    launch_scan_excl(g.cnt, ptrs[k], n, nullptr, nullptr, g.tmp, s);
-    launch_fill_int(g.cnt, 0, n, s);
-    if (m_cap > 0) incidence_fill<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, ptrs[k], g.cnt, g.raw);
-    launch_segment_sort(ptrs[k], g.raw, idxs[k], n, s);
-  }
+  launch_incidence(src, dst, m_cap, d_m, n, g, s);
   const int ngrid = (int)std::min<int64_t>((n + MT - 1) / MT, (int64_t)n_cu * 4);
   const int64_t etiles = (m_cap + MT - 1) / MT;
   const int egrid = (int)std::min<int64_t>(etiles, (int64_t)n_cu * 4);
@@ -470,6 +458,22 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
 }
 
 }  // namespace
+
+void launch_incidence(const int* src, const int* dst, int64_t m_cap, const int* d_m, int n, GnnScratch& g,
+                      hipStream_t s) {
+  const int* keys[2] = {src, dst};
+  int* ptrs[2] = {g.rowptr, g.cscptr};
+  int* idxs[2] = {g.rowidx, g.cscidx};
+  const int eb = blocks_for(m_cap, 256, 2048);
+  for (int k = 0; k < 2; ++k) {
+    launch_fill_int(g.cnt, 0, n, s);
+    if (m_cap > 0) incidence_count<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, g.cnt);
+    launch_scan_excl(g.cnt, ptrs[k], n, nullptr, nullptr, g.tmp, s);
+    launch_fill_int(g.cnt, 0, n, s);
+    if (m_cap > 0) incidence_fill<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, ptrs[k], g.cnt, g.raw);
+    launch_segment_sort(ptrs[k], g.raw, idxs[k], n, s);
+  }
+}
 
 int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {

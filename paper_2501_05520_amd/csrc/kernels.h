@@ -89,6 +89,9 @@ struct GnnScratch {
   int* cnt = nullptr;        // [n] per-dst counts / cursors
   int* tmp = nullptr;        // scan scratch
 };
+// CSR (by src) and CSC (by dst) incidence lists of the edges into g, edge ids ascending per node
+void launch_incidence(const int* src, const int* dst, int64_t m_cap, const int* d_m, int n, GnnScratch& g,
+                      hipStream_t s);
 int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s);
 

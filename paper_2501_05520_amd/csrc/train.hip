@@ -1,0 +1,817 @@
+// Training path of the filter MLP and the interaction network (FP32): forward
+// passes that keep what the backward needs, hand-written backward passes, the
+// binary cross-entropy objective and an Adam update.
+//
+// Objective (the reading taken for the training configuration): mean binary
+// cross-entropy with logits on the generator truth over the candidate edges
+// (filter) plus the same over the filtered edges (interaction network); edge
+// sets are held fixed.  The interaction-network backward keeps only the
+// per-iteration node and edge states (h^t, e^t) from the forward pass and
+// recomputes each iteration's internals from (h^{t-1}, e^{t-1}) when it gets
+// there, so activation memory is (T+1) state copies instead of every layer of
+// every iteration.
+//
+// Building blocks, all on MFMA (v_mfma_f32_16x16x4_f32) or plain vector code:
+//   rowgemm : out[r][:] = epi(X[r][:] W) for a row-major X (epilogues: store,
+//             accumulate, +bias, tanh(+bias), times (1 - aux^2));
+//   wgrad   : G[K(+1)][N] += X^T D over all rows, split over row chunks, partial
+//             sums reduced in a fixed order (deterministic), the optional extra
+//             row K being the bias gradient (column sums of D);
+//   segsum  : per-node sums of edge rows over the CSR/CSC incidence lists (the
+//             backward of a gather is again a fixed-order gather);
+// the transposed weights needed by backward products are kept as their own
+// fragment blocks, rebuilt with the forward ones whenever parameters change.
+#include <vector>
+
+#include "common.h"
+#include "ctx.h"
+#include "mfma_tile.h"
+
+namespace {
+
+enum { EPI_STORE = 0, EPI_ACC = 1, EPI_BIAS = 2, EPI_BIAS_TANH = 3, EPI_DTANH = 4 };
+
+// ---------------------------------------------------------------------------
+// fragment blocks from a view of parameter memory
+// ---------------------------------------------------------------------------
+struct MatView {
+  const float* p = nullptr;  // base
+  int r0 = 0;                // first row of the block in the stored matrix
+  int ld = 0;                // row stride of the stored matrix
+  int trans = 0;             // element (k, n) = trans ? p[(r0 + n) ld + k] : p[(r0 + k) ld + n]
+  __device__ float at(int k, int n) const {
+    return trans ? p[(size_t)(r0 + n) * ld + k] : p[(size_t)(r0 + k) * ld + n];
+  }
+};
+
+// M[k][n] for k < K, n < N, built from A and B: mode 0 = A only, 1 = [A | B] side by side
+// (B from column N1), 2 = [A ; B] stacked (B from row K1).
+__global__ void frag_fill_kernel(uint4* out, int nkb, int nnt, int K, int N, MatView A, MatView B, int mode, int split,
+                                 int bf16) {
+  const int64_t nblk = (int64_t)nkb * nnt * 64;
+  GRID_STRIDE(t, nblk) {
+    const int lane = (int)(t % 64);
+    const int64_t blk = t / 64;
+    const int kb = (int)(blk % nkb), nt = (int)(blk / nkb);
+    const int g = lane >> 4, n = nt * 16 + (lane & 15);
+    auto val = [&](int k) -> float {
+      if (k >= K || n >= N) return 0.f;
+      if (mode == 1 && n >= split) return B.at(k, n - split);
+      if (mode == 2 && k >= split) return B.at(k - split, n);
+      return A.at(k, n);
+    };
+    uint4 o;
+    if (!bf16) {
+      float v[4];
+      for (int s = 0; s < 4; ++s) v[s] = val(kb * 16 + 4 * g + s);
+      o = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]), __float_as_uint(v[3]));
+    } else {
+      bf16x8 v;
+      for (int j = 0; j < 8; ++j) v[j] = (__bf16)val(kb * 32 + 8 * g + j);
+      o = __builtin_bit_cast(uint4, v);
+    }
+    out[t] = o;
+  }
+}
+
+__global__ void bias_fill_kernel(float* out, int nout, const float* b, int N) {
+  GRID_STRIDE(i, nout) out[i] = i < N ? b[i] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// rowgemm: out = epi(X W), X [m][K] row-major (ldx), W fragment blocks (FP32)
+// ---------------------------------------------------------------------------
+constexpr int RG_MT = 64, RG_NW = 4, RG_KMAX = 512;
+
+template <int NTW>
+__global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __restrict__ X, int ldx, int K, int64_t m,
+                                                             DevLayer W, float* __restrict__ out, int ldo, int N,
+                                                             int epi, const float* __restrict__ aux, int ldaux) {
+  constexpr int LDX = RG_KMAX + 4;
+  __shared__ __align__(16) float xs[RG_MT * LDX];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int kpad = W.nkb * 16;
+  const int64_t ntiles = (m + RG_MT - 1) / RG_MT;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * RG_MT;
+    for (int idx = threadIdx.x; idx < RG_MT * kpad; idx += blockDim.x) {
+      const int mm = idx / kpad, k = idx - mm * kpad;
+      xs[mm * LDX + k] = (row0 + mm < m && k < K) ? X[(size_t)(row0 + mm) * ldx + k] : 0.f;
+    }
+    __syncthreads();
+    for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
+      f32x4 acc[4][NTW];
+      acc_zero(acc);
+      tile_gemm<PrecF32, 4, NTW>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const int n0 = (nt0 + j) * 16 + 4 * g;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t row = row0 + i * 16 + r;
+          if (row >= m) continue;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int n = n0 + c;
+            if (n >= N) continue;
+            float v = acc[i][j][c];
+            float* o = out + (size_t)row * ldo + n;
+            if (epi == EPI_ACC) v += *o;
+            else if (epi == EPI_BIAS) v += W.b[n];
+            else if (epi == EPI_BIAS_TANH) v = trk_tanh(v + W.b[n]);
+            else if (epi == EPI_DTANH) {
+              const float a = aux[(size_t)row * ldaux + n];
+              v *= 1.f - a * a;
+            }
+            *o = v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wgrad: partial[chunk][k][n] = sum over the chunk's rows of X[r][k] D[r][n]; row K of
+// the output is the column sum of D when with_bias.  X is dense (ldx) or, with
+// gsrc, the pair [S[gsrc[r]], S[gdst[r]]] of width 2*gd.
+// ---------------------------------------------------------------------------
+constexpr int WG_T = 64;   // tile edge (k and n)
+constexpr int WG_R = 64;   // rows staged per step
+
+__global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X, int ldx, const int* __restrict__ gsrc,
+                                                    const int* __restrict__ gdst, const float* __restrict__ S, int gd,
+                                                    int K, int with_bias, const float* __restrict__ Dm, int ldd, int N,
+                                                    int64_t m, int64_t rows_per_chunk, float* __restrict__ partial) {
+  __shared__ float xs[WG_R][WG_T + 1];
+  __shared__ float ds[WG_R][WG_T + 1];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int k0 = blockIdx.x * WG_T, n0 = blockIdx.y * WG_T;
+  const int Kb = K + (with_bias ? 1 : 0);
+  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t rend = min(m, rbeg + rows_per_chunk);
+  f32x4 acc[4];
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
+    for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
+      const int rr = idx / WG_T, c = idx - rr * WG_T;
+      const int64_t row = rs + rr;
+      const int k = k0 + c, n = n0 + c;
+      float xv = 0.f, dv = 0.f;
+      if (row < rend) {
+        if (k < K) {
+          if (gsrc) xv = k < gd ? S[(size_t)gsrc[row] * gd + k] : S[(size_t)gdst[row] * gd + (k - gd)];
+          else xv = X[(size_t)row * ldx + k];
+        } else if (k == K && with_bias) {
+          xv = 1.f;
+        }
+        if (n < N) dv = Dm[(size_t)row * ldd + n];
+      }
+      xs[rr][c] = xv;
+      ds[rr][c] = dv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < WG_R; rr += 4) {
+      // operands: k-row fragment from X^T (row = wave*16 + r), n fragments from D
+      const float xa = xs[rr + g][wave * 16 + r];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float da = ds[rr + g][j * 16 + r];
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(da, xa, acc[j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // lane holds rows k = k0 + wave*16 + r, columns n = n0 + j*16 + 4g + c
+  const int k = k0 + wave * 16 + r;
+  if (k < Kb) {
+    float* P = partial + ((size_t)blockIdx.z * Kb + k) * N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int n = n0 + j * 16 + 4 * g + c;
+        if (n < N) P[n] = acc[j][c];
+      }
+  }
+}
+
+__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks, int64_t count, float* __restrict__ grad) {
+  GRID_STRIDE(i, count) {
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * count + i];
+    grad[i] += s;
+  }
+}
+
+// per-node sums of rows of M [m][H] over incidence lists (src, dst or both), fixed order
+__global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __restrict__ p1, const int* __restrict__ i1,
+                              const int* __restrict__ p2, const int* __restrict__ i2, int n, float* __restrict__ out,
+                              int ldo) {
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  const int l = lane_id();
+  for (int node = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); node < n; node += waves) {
+    for (int c = l; c < H; c += 64) {
+      float s = 0.f;
+      if (p1)
+        for (int k = p1[node]; k < p1[node + 1]; ++k) s += M[(size_t)i1[k] * H + c];
+      if (p2)
+        for (int k = p2[node]; k < p2[node + 1]; ++k) s += M[(size_t)i2[k] * H + c];
+      out[(size_t)node * ldo + c] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise kernels
+// ---------------------------------------------------------------------------
+// X[r] = [S[src[r]] | S[dst[r]]], width 2*d (ld = ldx)
+__global__ void pair_gather_kernel(const float* S, int d, const int* src, const int* dst, int64_t m, float* X, int ldx) {
+  GRID_STRIDE(i, m * 2 * d) {
+    const int64_t r = i / (2 * d);
+    const int c = (int)(i - r * 2 * d);
+    X[r * ldx + c] = c < d ? S[(size_t)src[r] * d + c] : S[(size_t)dst[r] * d + c - d];
+  }
+}
+// t = tanh(A + P[src][0:H] + P[dst][H:2H] + b)
+__global__ void pre_tanh_kernel(const float* A, const float* P, const float* b, const int* src, const int* dst, int64_t m,
+                                int H, float* t) {
+  GRID_STRIDE(i, m * H) {
+    const int64_t r = i / H;
+    const int c = (int)(i - r * H);
+    t[i] = trk_tanh(A[i] + P[(size_t)src[r] * 2 * H + c] + P[(size_t)dst[r] * 2 * H + H + c] + b[c]);
+  }
+}
+__global__ void add_kernel(const float* a, const float* b, float* out, int64_t count) {
+  GRID_STRIDE(i, count) out[i] = a[i] + b[i];
+}
+// out[r][0:H] = A[r], out[r][H:2H] = B[r]
+__global__ void concat_kernel(const float* A, const float* B, int64_t n, int H, float* out) {
+  GRID_STRIDE(i, n * 2 * H) {
+    const int64_t r = i / (2 * H);
+    const int c = (int)(i - r * 2 * H);
+    out[i] = c < H ? A[r * H + c] : B[r * H + c - H];
+  }
+}
+// de[e] += dm[src[e]] + dm[dst[e]]   (dm rows with stride ldm, H columns)
+__global__ void gather_add_kernel(const float* dm, int ldm, const int* src, const int* dst, int64_t m, int H, float* de) {
+  GRID_STRIDE(i, m * H) {
+    const int64_t r = i / H;
+    const int c = (int)(i - r * H);
+    de[i] += dm[(size_t)src[r] * ldm + c] + dm[(size_t)dst[r] * ldm + c];
+  }
+}
+// out[r][c] = dz[r] * w[c] * (1 - u[r][c]^2)
+__global__ void outgrad_kernel(const float* dz, const float* w, const float* u, int64_t m, int H, float* out) {
+  GRID_STRIDE(i, m * H) {
+    const int64_t r = i / H;
+    const int c = (int)(i - r * H);
+    const float a = u[i];
+    out[i] = dz[r] * w[c] * (1.f - a * a);
+  }
+}
+// out[r][c] = a[r][c] + b[r * ldb + c], c < H
+__global__ void add_cols_kernel(const float* a, const float* b, int ldb, int64_t n, int H, float* out) {
+  GRID_STRIDE(i, n * H) {
+    const int64_t r = i / H;
+    const int c = (int)(i - r * H);
+    out[i] = a[i] + b[(size_t)r * ldb + c];
+  }
+}
+// out = d * (1 - a^2)
+__global__ void dtanh_kernel(const float* d, const float* a, int64_t count, float* out) {
+  GRID_STRIDE(i, count) out[i] = d[i] * (1.f - a[i] * a[i]);
+}
+
+// bce: per-block partial loss sums (fixed order) and dz = (sigmoid(z) - y) / m
+__global__ __launch_bounds__(256) void bce_kernel(const float* z, const float* y, int64_t m, float* dz, float* part) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  GRID_STRIDE(i, m) {
+    const float zi = z[i], yi = y[i];
+    s += fmaxf(zi, 0.f) - zi * yi + log1pf(trk_exp(-fabsf(zi)));
+    dz[i] = (trk_sigmoid(zi) - yi) / (float)m;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void bce_sum_kernel(const float* part, int nb, int64_t m, float* loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *loss = m > 0 ? s / (float)m : 0.f;
+  }
+}
+
+__global__ void adam_kernel(float* p, const float* gr, float* mo, float* ve, int64_t count, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  GRID_STRIDE(i, count) {
+    const float gi = gr[i];
+    const float mi = b1 * mo[i] + (1.f - b1) * gi;
+    const float vi = b2 * ve[i] + (1.f - b2) * gi * gi;
+    mo[i] = mi;
+    ve[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// host side
+// ===========================================================================
+struct LayerOff {
+  int64_t w = 0, b = 0;  // float offsets of W[K][N] and b[N] in the flat parameter vector
+  int K = 0, N = 0;
+};
+
+struct TrainState {
+  int64_t n_params = 0;
+  std::vector<LayerOff> filt, ne, ee, en, nn, out;   // per network, per layer
+  // FP32 fragment blocks for the training products
+  void* fmem = nullptr;
+  std::vector<DevLayer> filtF;       // forward layers 0..L (last: K x 1)
+  std::vector<DevLayer> filtT;       // transposed hidden layers 1..L-1 (index l -> W_l^T)
+  DevLayer ne1, ne2, ee1, ee2, ec, eab, e2, n1, n2, oc, oab, o2;   // forward
+  DevLayer ne2T, ee2T, ecT, eabT, e2T, n1T, n2T, ocT, oabT;        // transposed
+  // buffers
+  Arena arena;
+  float *fx0 = nullptr, *fact = nullptr, *fdel0 = nullptr, *fdel1 = nullptr;
+  float *x6 = nullptr, *ea1 = nullptr, *na1 = nullptr, *hck = nullptr, *eck = nullptr;
+  float *P = nullptr, *pre = nullptr, *t1 = nullptr, *v = nullptr, *u = nullptr;
+  float *de = nullptr, *dpre = nullptr, *dpre1 = nullptr, *msg = nullptr, *nin = nullptr, *q1 = nullptr, *q2 = nullptr;
+  float *dh = nullptr, *dh2 = nullptr, *dq = nullptr, *dq1 = nullptr, *dnin = nullptr, *dP = nullptr, *tmpN = nullptr;
+  float* partial = nullptr;
+  int64_t partial_floats = 0;
+  float* bce_part = nullptr;
+  int64_t cap_c = 0, cap_f = 0, nmax = 0;
+};
+
+namespace {
+
+void offsets_for(const trk_config& k, TrainState& T) {
+  int64_t o = 0;
+  auto net = [&](std::vector<LayerOff>& v, std::initializer_list<int> dims) {
+    std::vector<int> d(dims);
+    for (size_t i = 0; i + 1 < d.size(); ++i) {
+      LayerOff L;
+      L.K = d[i];
+      L.N = d[i + 1];
+      L.w = o;
+      o += (int64_t)L.K * L.N;
+      L.b = o;
+      o += L.N;
+      v.push_back(L);
+    }
+  };
+  std::vector<int> fd;
+  fd.push_back(2 * k.emb_dim);
+  for (int i = 0; i < k.filt_layers; ++i) fd.push_back(k.filt_hidden);
+  fd.push_back(1);
+  {
+    int64_t dummy = 0;
+    (void)dummy;
+    for (size_t i = 0; i + 1 < fd.size(); ++i) {
+      LayerOff L;
+      L.K = fd[i];
+      L.N = fd[i + 1];
+      L.w = o;
+      o += (int64_t)L.K * L.N;
+      L.b = o;
+      o += L.N;
+      T.filt.push_back(L);
+    }
+  }
+  const int H = k.gnn_hidden;
+  net(T.ne, {3, H, H});
+  net(T.ee, {6, H, H});
+  net(T.en, {3 * H, H, H});
+  net(T.nn, {2 * H, H, H});
+  net(T.out, {3 * H, H, 1});
+  T.n_params = o;
+}
+
+size_t frag_bytes(int K, int N) { return (size_t)((K + 15) / 16) * ((N + 15) / 16) * 64 * 16; }
+
+struct FragAlloc {
+  std::vector<std::pair<DevLayer*, std::pair<int, int>>> req;
+  size_t total = 0;
+  void add(DevLayer& L, int K, int N) {
+    L.K = K;
+    L.N = N;
+    L.nkb = (K + 15) / 16;
+    L.nnt = (N + 15) / 16;
+    req.push_back({&L, {K, N}});
+    total += frag_bytes(K, N) + (size_t)L.nnt * 16 * 4 + 512;
+  }
+  void place(void* base) {
+    size_t off = 0;
+    for (auto& r : req) {
+      r.first->w = (const uint4*)((char*)base + off);
+      off += (frag_bytes(r.second.first, r.second.second) + 255) & ~(size_t)255;
+      r.first->b = (const float*)((char*)base + off);
+      off += ((size_t)r.first->nnt * 16 * 4 + 255) & ~(size_t)255;
+    }
+  }
+};
+
+void fill(const DevLayer& L, int K, int N, MatView A, MatView B, int mode, int split, const float* bias, int bf16,
+          hipStream_t s) {
+  const int64_t nblk = (int64_t)L.nkb * L.nnt * 64;
+  frag_fill_kernel<<<blocks_for(nblk, 256), 256, 0, s>>>((uint4*)L.w, L.nkb, L.nnt, K, N, A, B, mode, split, bf16);
+  bias_fill_kernel<<<blocks_for(L.nnt * 16, 256), 256, 0, s>>>((float*)L.b, L.nnt * 16, bias, bias ? N : 0);
+}
+
+MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
+  MatView v;
+  v.p = P + L.w;
+  v.r0 = r0;
+  v.ld = L.N;
+  v.trans = trans;
+  return v;
+}
+
+template <int NTW>
+void rowgemm_t(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
+               const float* aux, int ldaux, int n_cu, hipStream_t s) {
+  const int64_t tiles = (m + RG_MT - 1) / RG_MT;
+  const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
+  if (grid > 0) rowgemm_kernel<NTW><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+}
+
+void rowgemm(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
+             const float* aux, int ldaux, int n_cu, hipStream_t s) {
+  const int per_wave = (W.nnt + RG_NW - 1) / RG_NW;
+  if (per_wave <= 1) rowgemm_t<1>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  else if (per_wave <= 2) rowgemm_t<2>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  else rowgemm_t<4>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+}
+
+void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int K,
+           bool bias, const float* D, int ldd, int N, int64_t m, float* grad, hipStream_t s) {
+  const int Kb = K + (bias ? 1 : 0);
+  const int64_t count = (int64_t)Kb * N;
+  int chunks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (m + 16383) / 16384));
+  while (chunks > 1 && (int64_t)chunks * count > T.partial_floats) --chunks;
+  const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
+  dim3 grid((Kb + WG_T - 1) / WG_T, (N + WG_T - 1) / WG_T, chunks);
+  if (m > 0) {
+    wgrad_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, K, bias ? 1 : 0, D, ldd, N, m, rpc, T.partial);
+    wgrad_reduce_kernel<<<blocks_for(count, 256), 256, 0, s>>>(T.partial, chunks, count, grad);
+  }
+}
+
+void segsum(const float* M, int H, const int* p1, const int* i1, const int* p2, const int* i2, int n, float* out, int ldo,
+            hipStream_t s) {
+  segsum_kernel<<<blocks_for(n, 4, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo);
+}
+
+template <class K, class... A>
+void ew(K kernel, int64_t count, hipStream_t s, A... args) {
+  if (count > 0) kernel<<<blocks_for(count, 256, 8192), 256, 0, s>>>(args...);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// internal API used by trk_api.hip
+// ---------------------------------------------------------------------------
+int train_create(trk_ctx* c) {
+  const trk_config& k = c->cfg;
+  if (c->prec != TRK_PREC_F32) return TRK_E_INVAL;
+  TrainState* T = new TrainState();
+  c->train = T;
+  offsets_for(k, *T);
+  const int H = k.gnn_hidden, F = k.filt_hidden, D = k.emb_dim, L = k.filt_layers;
+  FragAlloc fa;
+  T->filtF.resize(L + 1);
+  T->filtT.resize(L + 1);
+  for (int i = 0; i <= L; ++i) fa.add(T->filtF[i], T->filt[i].K, T->filt[i].N);
+  for (int i = 1; i < L; ++i) fa.add(T->filtT[i], F, F);
+  fa.add(T->ne1, 3, H); fa.add(T->ne2, H, H); fa.add(T->ee1, 6, H); fa.add(T->ee2, H, H);
+  fa.add(T->ec, H, H); fa.add(T->eab, H, 2 * H); fa.add(T->e2, H, H);
+  fa.add(T->n1, 2 * H, H); fa.add(T->n2, H, H);
+  fa.add(T->oc, H, H); fa.add(T->oab, H, 2 * H); fa.add(T->o2, H, 1);
+  fa.add(T->ne2T, H, H); fa.add(T->ee2T, H, H); fa.add(T->ecT, H, H); fa.add(T->eabT, 2 * H, H);
+  fa.add(T->e2T, H, H); fa.add(T->n1T, H, 2 * H); fa.add(T->n2T, H, H); fa.add(T->ocT, H, H);
+  fa.add(T->oabT, 2 * H, H);
+  if (hipMalloc(&T->fmem, fa.total) != hipSuccess) return TRK_E_NOMEM;
+  fa.place(T->fmem);
+  const int64_t CC = k.max_cand_edges, CF = k.max_kept_edges, NH = k.max_hits, It = k.gnn_iters;
+  T->cap_c = CC;
+  T->cap_f = CF;
+  T->nmax = NH;
+  Arena& a = T->arena;
+  a.add(T->fx0, (size_t)CC * 2 * D);
+  a.add(T->fact, (size_t)L * CC * F);
+  a.add(T->fdel0, (size_t)CC * F);
+  a.add(T->fdel1, (size_t)CC * F);
+  a.add(T->x6, (size_t)CF * 6);
+  a.add(T->ea1, (size_t)CF * H);
+  a.add(T->na1, (size_t)NH * H);
+  a.add(T->hck, (size_t)(It + 1) * NH * H);
+  a.add(T->eck, (size_t)(It + 1) * CF * H);
+  a.add(T->P, (size_t)NH * 2 * H);
+  for (float** p : {&T->pre, &T->t1, &T->v, &T->u, &T->de, &T->dpre, &T->dpre1}) a.add(*p, (size_t)CF * H);
+  a.add(T->msg, (size_t)NH * H);
+  a.add(T->nin, (size_t)NH * 2 * H);
+  for (float** p : {&T->q1, &T->q2, &T->dh, &T->dh2, &T->dq, &T->dq1, &T->tmpN}) a.add(*p, (size_t)NH * H);
+  a.add(T->dnin, (size_t)NH * 2 * H);
+  a.add(T->dP, (size_t)NH * 2 * H);
+  T->partial_floats = (int64_t)16 * 513 * 512;
+  a.add(T->partial, (size_t)T->partial_floats);
+  a.add(T->bce_part, 8192);
+  if (a.commit() != hipSuccess) return TRK_E_NOMEM;
+  return TRK_OK;
+}
+
+void train_destroy(trk_ctx* c) {
+  if (!c->train) return;
+  if (c->train->fmem) hipFree(c->train->fmem);
+  if (c->train->arena.base) hipFree(c->train->arena.base);
+  delete c->train;
+  c->train = nullptr;
+}
+
+int64_t train_param_count(const trk_config& k) {
+  TrainState T;
+  offsets_for(k, T);
+  return T.n_params;
+}
+
+// Rebuilds every FP32 fragment block (forward, transposed, and the inference
+// layers of the context) from the flat parameter vector P (device).
+int train_set_params(trk_ctx* c, const float* P, hipStream_t s) {
+  TrainState& T = *c->train;
+  const int H = c->cfg.gnn_hidden, L = c->cfg.filt_layers;
+  MatView none;
+  for (int i = 0; i <= L; ++i) {
+    const LayerOff& o = T.filt[i];
+    fill(T.filtF[i], o.K, o.N, view(P, o), none, 0, 0, P + o.b, 0, s);
+    if (i >= 1 && i < L) fill(T.filtT[i], o.N, o.K, view(P, o, 0, 1), none, 0, 0, nullptr, 0, s);
+  }
+  fill(T.ne1, 3, H, view(P, T.ne[0]), none, 0, 0, P + T.ne[0].b, 0, s);
+  fill(T.ne2, H, H, view(P, T.ne[1]), none, 0, 0, P + T.ne[1].b, 0, s);
+  fill(T.ee1, 6, H, view(P, T.ee[0]), none, 0, 0, P + T.ee[0].b, 0, s);
+  fill(T.ee2, H, H, view(P, T.ee[1]), none, 0, 0, P + T.ee[1].b, 0, s);
+  fill(T.ec, H, H, view(P, T.en[0], 2 * H), none, 0, 0, P + T.en[0].b, 0, s);
+  fill(T.eab, H, 2 * H, view(P, T.en[0], 0), view(P, T.en[0], H), 1, H, nullptr, 0, s);
+  fill(T.e2, H, H, view(P, T.en[1]), none, 0, 0, P + T.en[1].b, 0, s);
+  fill(T.n1, 2 * H, H, view(P, T.nn[0]), none, 0, 0, P + T.nn[0].b, 0, s);
+  fill(T.n2, H, H, view(P, T.nn[1]), none, 0, 0, P + T.nn[1].b, 0, s);
+  fill(T.oc, H, H, view(P, T.out[0], 2 * H), none, 0, 0, P + T.out[0].b, 0, s);
+  fill(T.oab, H, 2 * H, view(P, T.out[0], 0), view(P, T.out[0], H), 1, H, nullptr, 0, s);
+  fill(T.o2, H, 1, view(P, T.out[1]), none, 0, 0, P + T.out[1].b, 0, s);
+  // transposed: element (k, n) of W^T is W[n][k]
+  fill(T.ne2T, H, H, view(P, T.ne[1], 0, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.ee2T, H, H, view(P, T.ee[1], 0, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.ecT, H, H, view(P, T.en[0], 2 * H, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.eabT, 2 * H, H, view(P, T.en[0], 0, 1), view(P, T.en[0], H, 1), 2, H, nullptr, 0, s);
+  fill(T.e2T, H, H, view(P, T.en[1], 0, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.n1T, H, 2 * H, view(P, T.nn[0], 0, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.n2T, H, H, view(P, T.nn[1], 0, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.ocT, H, H, view(P, T.out[0], 2 * H, 1), none, 0, 0, nullptr, 0, s);
+  fill(T.oabT, 2 * H, H, view(P, T.out[0], 0, 1), view(P, T.out[0], H, 1), 2, H, nullptr, 0, s);
+  // the context's inference layers (FP32 context): same blocks as the forward ones
+  auto same = [&](DevLayer& dst, const LayerOff& o, int r0, int K, MatView B = MatView(), int mode = 0) {
+    fill(dst, K, o.N * (mode == 1 ? 2 : 1), view(P, o, r0), B, mode, o.N, mode == 1 ? nullptr : P + o.b, 0, s);
+  };
+  same(c->filt_in, T.filt[0], 0, T.filt[0].K);
+  for (int i = 1; i < L; ++i) same(c->filt_hid.l[i - 1], T.filt[i], 0, T.filt[i].K);
+  DevGNN& G = c->gnn;
+  same(G.node_enc1, T.ne[0], 0, 3);
+  same(G.node_enc2, T.ne[1], 0, H);
+  same(G.edge_enc1, T.ee[0], 0, 6);
+  same(G.edge_enc2, T.ee[1], 0, H);
+  same(G.edge_c, T.en[0], 2 * H, H);
+  same(G.edge_ab, T.en[0], 0, H, view(P, T.en[0], H), 1);
+  same(G.edge_2, T.en[1], 0, H);
+  same(G.node_1, T.nn[0], 0, 2 * H);
+  same(G.node_2, T.nn[1], 0, H);
+  same(G.out_c, T.out[0], 2 * H, H);
+  same(G.out_ab, T.out[0], 0, H, view(P, T.out[0], H), 1);
+  // single-output layers: weight vectors and the scalar biases (read back to the host)
+  hipMemcpyAsync((void*)c->filt_out.w, P + T.filt[L].w, sizeof(float) * c->cfg.filt_hidden, hipMemcpyDeviceToDevice, s);
+  hipMemcpyAsync((void*)G.out_2.w, P + T.out[1].w, sizeof(float) * H, hipMemcpyDeviceToDevice, s);
+  float b2[2];
+  hipMemcpyAsync(&b2[0], P + T.filt[L].b, sizeof(float), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(&b2[1], P + T.out[1].b, sizeof(float), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return TRK_E_DEVICE;
+  c->filt_out.b = b2[0];
+  G.out_2.b = b2[1];
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+namespace {
+
+bool train_ready(trk_ctx* c) { return c && c->train; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t trk_train_param_count(const trk_config* cfg) {
+  if (!cfg) return -1;
+  return train_param_count(*cfg);
+}
+
+int trk_train_set_params(trk_ctx* c, const float* d_params, hipStream_t s) {
+  if (!train_ready(c) || !d_params) return TRK_E_INVAL;
+  return train_set_params(c, d_params, s);
+}
+
+int trk_filter_train_fwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, const int32_t* d_dst,
+                         int64_t m, float* d_logits, hipStream_t s) {
+  if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_c) return TRK_E_INVAL;
+  if (m > 0 && (!d_emb || !d_src || !d_dst || !d_logits)) return TRK_E_INVAL;
+  if (m == 0) return TRK_OK;
+  TrainState& T = *c->train;
+  const int D = c->cfg.emb_dim, F = c->cfg.filt_hidden, L = c->cfg.filt_layers;
+  ew(pair_gather_kernel, m * 2 * D, s, d_emb, D, d_src, d_dst, m, T.fx0, 2 * D);
+  const float* a = T.fx0;
+  int lda = 2 * D, K = 2 * D;
+  for (int i = 0; i < L; ++i) {
+    float* o = T.fact + (size_t)i * T.cap_c * F;
+    rowgemm(a, lda, K, m, T.filtF[i], o, F, F, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    a = o;
+    lda = F;
+    K = F;
+  }
+  rowgemm(a, F, F, m, T.filtF[L], d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s);
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, const int32_t* d_dst,
+                         int64_t m, const float* d_dlogits, float* d_grads, hipStream_t s) {
+  if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_c || !d_grads) return TRK_E_INVAL;
+  if (m > 0 && (!d_emb || !d_src || !d_dst || !d_dlogits)) return TRK_E_INVAL;
+  if (m == 0) return TRK_OK;
+  TrainState& T = *c->train;
+  const int D = c->cfg.emb_dim, F = c->cfg.filt_hidden, L = c->cfg.filt_layers;
+  const float* aL = T.fact + (size_t)(L - 1) * T.cap_c * F;
+  wgrad(T, aL, F, nullptr, nullptr, nullptr, 0, F, true, d_dlogits, 1, 1, m, d_grads + T.filt[L].w, s);
+  float* del = T.fdel0;
+  float* nxt = T.fdel1;
+  ew(outgrad_kernel, m * F, s, d_dlogits, c->filt_out.w, aL, m, F, del);
+  for (int i = L - 1; i >= 0; --i) {
+    if (i == 0)
+      wgrad(T, nullptr, 0, d_src, d_dst, d_emb, D, 2 * D, true, del, F, F, m, d_grads + T.filt[0].w, s);
+    else
+      wgrad(T, T.fact + (size_t)(i - 1) * T.cap_c * F, F, nullptr, nullptr, nullptr, 0, F, true, del, F, F, m,
+            d_grads + T.filt[i].w, s);
+    if (i >= 1) {
+      rowgemm(del, F, F, m, T.filtT[i], nxt, F, F, EPI_DTANH, T.fact + (size_t)(i - 1) * T.cap_c * F, F, c->n_cu, s);
+      std::swap(del, nxt);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const int32_t* d_dst, int64_t m,
+                      float* d_logits, hipStream_t s) {
+  if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_f || !d_x) return TRK_E_INVAL;
+  if (m > 0 && (!d_src || !d_dst || !d_logits)) return TRK_E_INVAL;
+  TrainState& T = *c->train;
+  GnnScratch& g = c->gs;
+  const int H = c->cfg.gnn_hidden, It = c->cfg.gnn_iters;
+  const int nn = (int)n;
+  launch_incidence(d_src, d_dst, m, nullptr, nn, g, s);
+  rowgemm(d_x, 3, 3, n, T.ne1, T.na1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+  rowgemm(T.na1, H, H, n, T.ne2, T.hck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+  ew(pair_gather_kernel, m * 6, s, d_x, 3, d_src, d_dst, m, T.x6, 6);
+  rowgemm(T.x6, 6, 6, m, T.ee1, T.ea1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+  rowgemm(T.ea1, H, H, m, T.ee2, T.eck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+  for (int t = 1; t <= It; ++t) {
+    const float* h = T.hck + (size_t)(t - 1) * T.nmax * H;
+    const float* e = T.eck + (size_t)(t - 1) * T.cap_f * H;
+    float* h_new = T.hck + (size_t)t * T.nmax * H;
+    float* e_new = T.eck + (size_t)t * T.cap_f * H;
+    rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, m, H, T.t1);
+    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    ew(add_kernel, m * H, s, e, T.v, e_new, m * H);
+    segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
+    ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
+    rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    ew(add_kernel, n * H, s, h, T.q2, h_new, n * H);
+  }
+  const float* hT = T.hck + (size_t)It * T.nmax * H;
+  const float* eT = T.eck + (size_t)It * T.cap_f * H;
+  rowgemm(hT, H, H, n, T.oab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
+  if (m > 0) {
+    rowgemm(eT, H, H, m, T.oc, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.oc.b, d_src, d_dst, m, H, T.u);
+    rowgemm(T.u, H, H, m, T.o2, d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s);
+  }
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const int32_t* d_dst, int64_t m,
+                      const float* d_dlogits, float* d_grads, hipStream_t s) {
+  if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_f || !d_x || !d_grads)
+    return TRK_E_INVAL;
+  if (m > 0 && (!d_src || !d_dst || !d_dlogits)) return TRK_E_INVAL;
+  TrainState& T = *c->train;
+  GnnScratch& g = c->gs;
+  const int H = c->cfg.gnn_hidden, It = c->cfg.gnn_iters;
+  const int nn = (int)n;
+  float* G = d_grads;
+  const float* hT = T.hck + (size_t)It * T.nmax * H;
+  const float* eT = T.eck + (size_t)It * T.cap_f * H;
+  // output head
+  wgrad(T, T.u, H, nullptr, nullptr, nullptr, 0, H, true, d_dlogits, 1, 1, m, G + T.out[1].w, s);
+  float* du = T.dpre1;
+  ew(outgrad_kernel, m * H, s, d_dlogits, c->gnn.out_2.w, T.u, m, H, du);
+  segsum(du, H, g.rowptr, g.rowidx, nullptr, nullptr, nn, T.dP, 2 * H, s);
+  segsum(du, H, g.cscptr, g.cscidx, nullptr, nullptr, nn, T.dP + H, 2 * H, s);
+  wgrad(T, hT, H, nullptr, nullptr, nullptr, 0, H, false, T.dP, 2 * H, H, n, G + T.out[0].w, s);
+  wgrad(T, hT, H, nullptr, nullptr, nullptr, 0, H, false, T.dP + H, 2 * H, H, n, G + T.out[0].w + (size_t)H * H, s);
+  wgrad(T, eT, H, nullptr, nullptr, nullptr, 0, H, true, du, H, H, m, G + T.out[0].w + (size_t)2 * H * H, s);
+  float* dh = T.dh;
+  float* dh2 = T.dh2;
+  rowgemm(T.dP, 2 * H, 2 * H, n, T.oabT, dh, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+  rowgemm(du, H, H, m, T.ocT, T.de, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+  for (int t = It; t >= 1; --t) {
+    const float* h = T.hck + (size_t)(t - 1) * T.nmax * H;
+    const float* e = T.eck + (size_t)(t - 1) * T.cap_f * H;
+    const float* e_new = T.eck + (size_t)t * T.cap_f * H;
+    // recompute this iteration's internals from (h^{t-1}, e^{t-1})
+    rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, m, H, T.t1);
+    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
+    ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
+    rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    // node update h^t = h + phi_v([h, msg])
+    ew(dtanh_kernel, n * H, s, dh, T.q2, n * H, T.dq);
+    wgrad(T, T.q1, H, nullptr, nullptr, nullptr, 0, H, true, T.dq, H, H, n, G + T.nn[1].w, s);
+    rowgemm(T.dq, H, H, n, T.n2T, T.dq1, H, H, EPI_DTANH, T.q1, H, c->n_cu, s);
+    wgrad(T, T.nin, 2 * H, nullptr, nullptr, nullptr, 0, 2 * H, true, T.dq1, H, H, n, G + T.nn[0].w, s);
+    rowgemm(T.dq1, H, H, n, T.n1T, T.dnin, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    ew(add_cols_kernel, n * H, s, dh, T.dnin, 2 * H, n, H, dh2);
+    // messages: de^t += dmsg[src] + dmsg[dst]
+    if (m > 0) ew(gather_add_kernel, m * H, s, T.dnin + H, 2 * H, d_src, d_dst, m, H, T.de);
+    // edge update e^t = e + phi_e([h_s, h_t, e])
+    ew(dtanh_kernel, m * H, s, T.de, T.v, m * H, T.dpre);
+    wgrad(T, T.t1, H, nullptr, nullptr, nullptr, 0, H, true, T.dpre, H, H, m, G + T.en[1].w, s);
+    rowgemm(T.dpre, H, H, m, T.e2T, T.dpre1, H, H, EPI_DTANH, T.t1, H, c->n_cu, s);
+    wgrad(T, e, H, nullptr, nullptr, nullptr, 0, H, true, T.dpre1, H, H, m, G + T.en[0].w + (size_t)2 * H * H, s);
+    segsum(T.dpre1, H, g.rowptr, g.rowidx, nullptr, nullptr, nn, T.dP, 2 * H, s);
+    segsum(T.dpre1, H, g.cscptr, g.cscidx, nullptr, nullptr, nn, T.dP + H, 2 * H, s);
+    wgrad(T, h, H, nullptr, nullptr, nullptr, 0, H, false, T.dP, 2 * H, H, n, G + T.en[0].w, s);
+    wgrad(T, h, H, nullptr, nullptr, nullptr, 0, H, false, T.dP + H, 2 * H, H, n, G + T.en[0].w + (size_t)H * H, s);
+    rowgemm(T.dpre1, H, H, m, T.ecT, T.de, H, H, EPI_ACC, nullptr, 0, c->n_cu, s);
+    rowgemm(T.dP, 2 * H, 2 * H, n, T.eabT, dh2, H, H, EPI_ACC, nullptr, 0, c->n_cu, s);
+    std::swap(dh, dh2);
+  }
+  // encoders
+  if (m > 0) {
+    ew(dtanh_kernel, m * H, s, T.de, T.eck, m * H, T.dpre);
+    wgrad(T, T.ea1, H, nullptr, nullptr, nullptr, 0, H, true, T.dpre, H, H, m, G + T.ee[1].w, s);
+    rowgemm(T.dpre, H, H, m, T.ee2T, T.dpre1, H, H, EPI_DTANH, T.ea1, H, c->n_cu, s);
+    wgrad(T, T.x6, 6, nullptr, nullptr, nullptr, 0, 6, true, T.dpre1, H, H, m, G + T.ee[0].w, s);
+  }
+  ew(dtanh_kernel, n * H, s, dh, T.hck, n * H, T.dq);
+  wgrad(T, T.na1, H, nullptr, nullptr, nullptr, 0, H, true, T.dq, H, H, n, G + T.ne[1].w, s);
+  rowgemm(T.dq, H, H, n, T.ne2T, T.dq1, H, H, EPI_DTANH, T.na1, H, c->n_cu, s);
+  wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 3, true, T.dq1, H, H, n, G + T.ne[0].w, s);
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_bce_with_logits(trk_ctx* c, const float* d_logits, const float* d_targets, int64_t m, float* d_dlogits,
+                        float* h_loss, hipStream_t s) {
+  if (!train_ready(c) || m < 0 || (m > 0 && (!d_logits || !d_targets || !d_dlogits))) return TRK_E_INVAL;
+  if (h_loss) *h_loss = 0.f;
+  if (m == 0) return TRK_OK;
+  TrainState& T = *c->train;
+  const int nb = blocks_for(m, 256, 4096);
+  bce_kernel<<<nb, 256, 0, s>>>(d_logits, d_targets, m, d_dlogits, T.bce_part);
+  bce_sum_kernel<<<1, 64, 0, s>>>(T.bce_part, nb, m, T.bce_part + 4096);
+  if (h_loss) {
+    if (hipMemcpyAsync(h_loss, T.bce_part + 4096, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return TRK_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return TRK_E_DEVICE;
+  }
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_adam_update(trk_ctx* c, float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t count, float lr,
+                    float beta1, float beta2, float eps, int64_t step, hipStream_t s) {
+  if (!c || count < 0 || step < 1 || (count > 0 && (!d_params || !d_grads || !d_m || !d_v))) return TRK_E_INVAL;
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  if (count > 0) ew(adam_kernel, count, s, d_params, d_grads, d_m, d_v, count, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+}  // extern "C"

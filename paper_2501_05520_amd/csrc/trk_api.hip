@@ -11,6 +11,7 @@
 #include "../../include/trk.h"
 #include "kernels.h"
 #include "common.h"
+#include "ctx.h"
 
 namespace {
 
@@ -61,66 +62,7 @@ std::vector<uint8_t> make_fragments(const float* w, int K, int N, int prec, int&
   return out;
 }
 
-// ---------------------------------------------------------------------------
-// device arena: one allocation carved into 256-byte aligned pieces
-// ---------------------------------------------------------------------------
-struct Arena {
-  std::vector<std::pair<void**, size_t>> req;
-  void* base = nullptr;
-  size_t total = 0;
-  template <class T>
-  void add(T*& p, size_t count) { req.push_back({(void**)&p, count * sizeof(T)}); }
-  void add_bytes(void*& p, size_t bytes) { req.push_back({&p, bytes}); }
-  hipError_t commit() {
-    total = 0;
-    for (auto& r : req) total += (r.second + 255) & ~(size_t)255;
-    if (total == 0) total = 256;
-    hipError_t e = hipMalloc(&base, total);
-    if (e != hipSuccess) return e;
-    size_t off = 0;
-    for (auto& r : req) {
-      *r.first = (char*)base + off;
-      off += (r.second + 255) & ~(size_t)255;
-    }
-    return hipSuccess;
-  }
-};
-
 }  // namespace
-
-struct trk_ctx {
-  trk_config cfg;
-  int device = 0;
-  int n_cu = 256;
-  int prec = TRK_PREC_F32;
-  hipStream_t own_stream = nullptr;
-  // weights
-  void* wmem = nullptr;
-  DevLayer emb_in, emb_out;
-  LayerList emb_hid;
-  DevLayer filt_in;
-  LayerList filt_hid;
-  DevVec filt_out;
-  DevGNN gnn;
-  // scratch
-  Arena arena;
-  float* emb = nullptr;
-  int* cand_src = nullptr;
-  int* cand_dst = nullptr;
-  float* cand_scores = nullptr;
-  int* filt_src = nullptr;
-  int* filt_dst = nullptr;
-  float* gnn_scores = nullptr;
-  int* ev = nullptr;
-  int64_t* offs = nullptr;
-  int* dev_words = nullptr;  // [16]: 0 err bits, 1 filtered count, 2 kept count, 3.. per-event use
-  int* batch_counts = nullptr;  // [max_events][4] per-event counts
-  GraphScratch graph;
-  GnnScratch gs;
-  int* host_words = nullptr;  // pinned mirror
-  hipEvent_t ev_stage[8] = {};
-  bool timing = false;
-};
 
 namespace {
 
@@ -447,6 +389,7 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
   rc = load_weights(c, h_weights, nbytes);
   if (!rc) rc = alloc_scratch(c);
   c->timing = cfg->stage_timing != 0;
+  if (!rc && cfg->training) rc = train_create(c);
   for (int i = 0; i < 8 && !rc && c->timing; ++i)
     if (hipEventCreate(&c->ev_stage[i]) != hipSuccess) rc = TRK_E_DEVICE;
   if (rc) {
@@ -461,6 +404,7 @@ void trk_destroy(trk_ctx* c) {
   if (!c) return;
   DeviceGuard guard(c->device);
   hipDeviceSynchronize();
+  train_destroy(c);
   if (c->arena.base) hipFree(c->arena.base);
   if (c->wmem) hipFree(c->wmem);
   if (c->host_words) hipHostFree(c->host_words);

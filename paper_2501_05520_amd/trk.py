@@ -21,7 +21,9 @@ STATUS = {0: "TRK_OK", -1: "TRK_E_INVAL", -2: "TRK_E_NOMEM", -3: "TRK_E_CAPACITY
 EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_filter", "trk_gnn",
            "trk_components", "trk_event", "trk_batch", "trk_strerror",
            "trk_server_create", "trk_server_submit", "trk_server_wait", "trk_server_stats",
-           "trk_server_destroy")
+           "trk_server_destroy", "trk_train_param_count", "trk_train_set_params", "trk_filter_train_fwd",
+           "trk_filter_train_bwd", "trk_gnn_train_fwd", "trk_gnn_train_bwd", "trk_bce_with_logits",
+           "trk_adam_update")
 
 
 class TrkError(RuntimeError):
@@ -40,7 +42,7 @@ class trk_config(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("max_hits", ctypes.c_int64), ("max_cand_edges", ctypes.c_int64),
                 ("max_kept_edges", ctypes.c_int64), ("max_events", ctypes.c_int32),
-                ("stage_timing", ctypes.c_int32)]
+                ("stage_timing", ctypes.c_int32), ("training", ctypes.c_int32)]
 
 
 class trk_event_info(ctypes.Structure):
@@ -101,11 +103,20 @@ def lib():
         L.trk_server_stats.argtypes = [P, ctypes.POINTER(trk_server_info)]
         L.trk_server_destroy.argtypes = [P]
         L.trk_server_destroy.restype = None
+        L.trk_train_param_count.argtypes = [ctypes.POINTER(trk_config)]
+        L.trk_train_set_params.argtypes = [P, P, P]
+        L.trk_filter_train_fwd.argtypes = [P, P, I64, P, P, I64, P, P]
+        L.trk_filter_train_bwd.argtypes = [P, P, I64, P, P, I64, P, P, P]
+        L.trk_gnn_train_fwd.argtypes = [P, P, I64, P, P, I64, P, P]
+        L.trk_gnn_train_bwd.argtypes = [P, P, I64, P, P, I64, P, P, P]
+        L.trk_bce_with_logits.argtypes = [P, P, P, I64, P, ctypes.POINTER(F), P]
+        L.trk_adam_update.argtypes = [P, P, P, P, P, I64, F, F, F, F, I64, P]
         L.trk_strerror.argtypes = [ctypes.c_int]
         L.trk_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name not in ("trk_destroy", "trk_strerror", "trk_server_destroy"):
                 getattr(L, name).restype = ctypes.c_int
+        L.trk_train_param_count.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -134,7 +145,7 @@ def _stream(stream=None):
 # configuration and weights
 # ---------------------------------------------------------------------------
 def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max_kept_edges=None, max_events=1,
-                stage_timing=False):
+                stage_timing=False, training=False):
     """trk_config from an object with the network and pipeline attributes
     (emb_hidden, emb_layers, emb_dim, filt_hidden, filt_layers, gnn_hidden,
     gnn_iters, radius, k_max, filter_cut, score_cut)."""
@@ -146,7 +157,7 @@ def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max
     return trk_config(TRK_ABI_VERSION, cfg.emb_hidden, cfg.emb_layers, cfg.emb_dim, cfg.filt_hidden,
                       cfg.filt_layers, cfg.gnn_hidden, cfg.gnn_iters, float(cfg.radius), cfg.k_max,
                       float(cfg.filter_cut), float(cfg.score_cut), int(precision), max_hits, cand, kept,
-                      int(max_events), int(bool(stage_timing)))
+                      int(max_events), int(bool(stage_timing)), int(bool(training)))
 
 
 NET_ORDER = ("emb", "filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
@@ -391,3 +402,74 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# training entry points
+# ---------------------------------------------------------------------------
+TRAIN_NETS = ("filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
+
+
+def trk_train_param_count(config):
+    return int(lib().trk_train_param_count(ctypes.byref(config)))
+
+
+def flatten_params(nets):
+    """Flat FP32 parameter vector of the trained networks (C-ABI layout)."""
+    parts = []
+    for name in TRAIN_NETS:
+        for w, b in nets[name]:
+            parts += [np.ascontiguousarray(w, np.float32).reshape(-1), np.ascontiguousarray(b, np.float32)]
+    return np.concatenate(parts)
+
+
+def unflatten_params(vec, nets_like):
+    """Inverse of flatten_params, shaped like nets_like (numpy)."""
+    vec = np.asarray(vec)
+    out, o = {}, 0
+    for name in TRAIN_NETS:
+        layers = []
+        for w, b in nets_like[name]:
+            W = vec[o:o + w.size].reshape(w.shape); o += w.size
+            B = vec[o:o + b.size]; o += b.size
+            layers.append((W, B))
+        out[name] = layers
+    assert o == vec.size
+    return out
+
+
+def trk_train_set_params(ctx, params, stream=None):
+    _check(lib().trk_train_set_params(ctx, _ptr(params), _stream(stream)), "trk_train_set_params")
+
+
+def trk_filter_train_fwd(ctx, emb, src, dst, logits, stream=None):
+    _check(lib().trk_filter_train_fwd(ctx, _ptr(emb), emb.shape[0], _ptr(src), _ptr(dst), src.numel(), _ptr(logits),
+                                      _stream(stream)), "trk_filter_train_fwd")
+
+
+def trk_filter_train_bwd(ctx, emb, src, dst, dlogits, grads, stream=None):
+    _check(lib().trk_filter_train_bwd(ctx, _ptr(emb), emb.shape[0], _ptr(src), _ptr(dst), src.numel(),
+                                      _ptr(dlogits), _ptr(grads), _stream(stream)), "trk_filter_train_bwd")
+
+
+def trk_gnn_train_fwd(ctx, x, src, dst, logits, stream=None):
+    _check(lib().trk_gnn_train_fwd(ctx, _ptr(x), x.shape[0], _ptr(src), _ptr(dst), src.numel(), _ptr(logits),
+                                   _stream(stream)), "trk_gnn_train_fwd")
+
+
+def trk_gnn_train_bwd(ctx, x, src, dst, dlogits, grads, stream=None):
+    _check(lib().trk_gnn_train_bwd(ctx, _ptr(x), x.shape[0], _ptr(src), _ptr(dst), src.numel(), _ptr(dlogits),
+                                   _ptr(grads), _stream(stream)), "trk_gnn_train_bwd")
+
+
+def trk_bce_with_logits(ctx, logits, targets, dlogits, stream=None):
+    loss = ctypes.c_float()
+    _check(lib().trk_bce_with_logits(ctx, _ptr(logits), _ptr(targets), logits.numel(), _ptr(dlogits),
+                                     ctypes.byref(loss), _stream(stream)), "trk_bce_with_logits")
+    return loss.value
+
+
+def trk_adam_update(ctx, params, grads, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _check(lib().trk_adam_update(ctx, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), float(lr),
+                                 float(beta1), float(beta2), float(eps), int(step), _stream(stream)),
+           "trk_adam_update")

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "trk.h")
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(trk_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:int|int64_t|void|const char\*)\s+(trk_\w+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
