@@ -31,6 +31,10 @@ namespace {
 
 enum { EPI_STORE = 0, EPI_ACC = 1, EPI_BIAS = 2, EPI_BIAS_TANH = 3, EPI_DTANH = 4 };
 
+// node index clamped into [0, n): an out-of-range edge end reads node 0 instead of
+// memory past the node arrays (the inference entry points report such edges)
+__device__ __forceinline__ size_t node_of(int i, int n) { return (unsigned)i < (unsigned)n ? (size_t)i : 0; }
+
 // ---------------------------------------------------------------------------
 // fragment blocks from a view of parameter memory
 // ---------------------------------------------------------------------------
@@ -142,7 +146,7 @@ constexpr int WG_R = 64;   // rows staged per step
 
 __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X, int ldx, const int* __restrict__ gsrc,
                                                     const int* __restrict__ gdst, const float* __restrict__ S, int gd,
-                                                    int K, int with_bias, const float* __restrict__ Dm, int ldd, int N,
+                                                    int gn, int K, int with_bias, const float* __restrict__ Dm, int ldd, int N,
                                                     int64_t m, int64_t rows_per_chunk, float* __restrict__ partial) {
   __shared__ float xs[WG_R][WG_T + 1];
   __shared__ float ds[WG_R][WG_T + 1];
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X,
       float xv = 0.f, dv = 0.f;
       if (row < rend) {
         if (k < K) {
-          if (gsrc) xv = k < gd ? S[(size_t)gsrc[row] * gd + k] : S[(size_t)gdst[row] * gd + (k - gd)];
+          if (gsrc) xv = k < gd ? S[node_of(gsrc[row], gn) * gd + k] : S[node_of(gdst[row], gn) * gd + (k - gd)];
           else xv = X[(size_t)row * ldx + k];
         } else if (k == K && with_bias) {
           xv = 1.f;
@@ -228,20 +232,21 @@ __global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __r
 // elementwise kernels
 // ---------------------------------------------------------------------------
 // X[r] = [S[src[r]] | S[dst[r]]], width 2*d (ld = ldx)
-__global__ void pair_gather_kernel(const float* S, int d, const int* src, const int* dst, int64_t m, float* X, int ldx) {
+__global__ void pair_gather_kernel(const float* S, int d, int n, const int* src, const int* dst, int64_t m, float* X,
+                                   int ldx) {
   GRID_STRIDE(i, m * 2 * d) {
     const int64_t r = i / (2 * d);
     const int c = (int)(i - r * 2 * d);
-    X[r * ldx + c] = c < d ? S[(size_t)src[r] * d + c] : S[(size_t)dst[r] * d + c - d];
+    X[r * ldx + c] = c < d ? S[node_of(src[r], n) * d + c] : S[node_of(dst[r], n) * d + c - d];
   }
 }
 // t = tanh(A + P[src][0:H] + P[dst][H:2H] + b)
-__global__ void pre_tanh_kernel(const float* A, const float* P, const float* b, const int* src, const int* dst, int64_t m,
-                                int H, float* t) {
+__global__ void pre_tanh_kernel(const float* A, const float* P, const float* b, const int* src, const int* dst, int n,
+                                int64_t m, int H, float* t) {
   GRID_STRIDE(i, m * H) {
     const int64_t r = i / H;
     const int c = (int)(i - r * H);
-    t[i] = trk_tanh(A[i] + P[(size_t)src[r] * 2 * H + c] + P[(size_t)dst[r] * 2 * H + H + c] + b[c]);
+    t[i] = trk_tanh(A[i] + P[node_of(src[r], n) * 2 * H + c] + P[node_of(dst[r], n) * 2 * H + H + c] + b[c]);
   }
 }
 __global__ void add_kernel(const float* a, const float* b, float* out, int64_t count) {
@@ -256,11 +261,12 @@ __global__ void concat_kernel(const float* A, const float* B, int64_t n, int H, 
   }
 }
 // de[e] += dm[src[e]] + dm[dst[e]]   (dm rows with stride ldm, H columns)
-__global__ void gather_add_kernel(const float* dm, int ldm, const int* src, const int* dst, int64_t m, int H, float* de) {
+__global__ void gather_add_kernel(const float* dm, int ldm, const int* src, const int* dst, int n, int64_t m, int H,
+                                  float* de) {
   GRID_STRIDE(i, m * H) {
     const int64_t r = i / H;
     const int c = (int)(i - r * H);
-    de[i] += dm[(size_t)src[r] * ldm + c] + dm[(size_t)dst[r] * ldm + c];
+    de[i] += dm[node_of(src[r], n) * ldm + c] + dm[node_of(dst[r], n) * ldm + c];
   }
 }
 // out[r][c] = dz[r] * w[c] * (1 - u[r][c]^2)
@@ -454,8 +460,8 @@ void rowgemm(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float
   else rowgemm_t<4>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
 }
 
-void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int K,
-           bool bias, const float* D, int ldd, int N, int64_t m, float* grad, hipStream_t s) {
+void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int gn,
+           int K, bool bias, const float* D, int ldd, int N, int64_t m, float* grad, hipStream_t s) {
   const int Kb = K + (bias ? 1 : 0);
   const int64_t count = (int64_t)Kb * N;
   int chunks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (m + 16383) / 16384));
@@ -463,7 +469,7 @@ void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* g
   const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
   dim3 grid((Kb + WG_T - 1) / WG_T, (N + WG_T - 1) / WG_T, chunks);
   if (m > 0) {
-    wgrad_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, K, bias ? 1 : 0, D, ldd, N, m, rpc, T.partial);
+    wgrad_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N, m, rpc, T.partial);
     wgrad_reduce_kernel<<<blocks_for(count, 256), 256, 0, s>>>(T.partial, chunks, count, grad);
   }
 }
@@ -634,7 +640,7 @@ int trk_filter_train_fwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
   if (m == 0) return TRK_OK;
   TrainState& T = *c->train;
   const int D = c->cfg.emb_dim, F = c->cfg.filt_hidden, L = c->cfg.filt_layers;
-  ew(pair_gather_kernel, m * 2 * D, s, d_emb, D, d_src, d_dst, m, T.fx0, 2 * D);
+  ew(pair_gather_kernel, m * 2 * D, s, d_emb, D, (int)n, d_src, d_dst, m, T.fx0, 2 * D);
   const float* a = T.fx0;
   int lda = 2 * D, K = 2 * D;
   for (int i = 0; i < L; ++i) {
@@ -656,15 +662,15 @@ int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
   TrainState& T = *c->train;
   const int D = c->cfg.emb_dim, F = c->cfg.filt_hidden, L = c->cfg.filt_layers;
   const float* aL = T.fact + (size_t)(L - 1) * T.cap_c * F;
-  wgrad(T, aL, F, nullptr, nullptr, nullptr, 0, F, true, d_dlogits, 1, 1, m, d_grads + T.filt[L].w, s);
+  wgrad(T, aL, F, nullptr, nullptr, nullptr, 0, 0, F, true, d_dlogits, 1, 1, m, d_grads + T.filt[L].w, s);
   float* del = T.fdel0;
   float* nxt = T.fdel1;
   ew(outgrad_kernel, m * F, s, d_dlogits, c->filt_out.w, aL, m, F, del);
   for (int i = L - 1; i >= 0; --i) {
     if (i == 0)
-      wgrad(T, nullptr, 0, d_src, d_dst, d_emb, D, 2 * D, true, del, F, F, m, d_grads + T.filt[0].w, s);
+      wgrad(T, nullptr, 0, d_src, d_dst, d_emb, D, (int)n, 2 * D, true, del, F, F, m, d_grads + T.filt[0].w, s);
     else
-      wgrad(T, T.fact + (size_t)(i - 1) * T.cap_c * F, F, nullptr, nullptr, nullptr, 0, F, true, del, F, F, m,
+      wgrad(T, T.fact + (size_t)(i - 1) * T.cap_c * F, F, nullptr, nullptr, nullptr, 0, 0, F, true, del, F, F, m,
             d_grads + T.filt[i].w, s);
     if (i >= 1) {
       rowgemm(del, F, F, m, T.filtT[i], nxt, F, F, EPI_DTANH, T.fact + (size_t)(i - 1) * T.cap_c * F, F, c->n_cu, s);
@@ -685,7 +691,7 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   launch_incidence(d_src, d_dst, m, nullptr, nn, g, s);
   rowgemm(d_x, 3, 3, n, T.ne1, T.na1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
   rowgemm(T.na1, H, H, n, T.ne2, T.hck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
-  ew(pair_gather_kernel, m * 6, s, d_x, 3, d_src, d_dst, m, T.x6, 6);
+  ew(pair_gather_kernel, m * 6, s, d_x, 3, nn, d_src, d_dst, m, T.x6, 6);
   rowgemm(T.x6, 6, 6, m, T.ee1, T.ea1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
   rowgemm(T.ea1, H, H, m, T.ee2, T.eck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
   for (int t = 1; t <= It; ++t) {
@@ -695,7 +701,7 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
     float* e_new = T.eck + (size_t)t * T.cap_f * H;
     rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
     rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
-    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, m, H, T.t1);
+    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
     rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
     ew(add_kernel, m * H, s, e, T.v, e_new, m * H);
     segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
@@ -709,7 +715,7 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   rowgemm(hT, H, H, n, T.oab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
   if (m > 0) {
     rowgemm(eT, H, H, m, T.oc, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
-    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.oc.b, d_src, d_dst, m, H, T.u);
+    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.oc.b, d_src, d_dst, nn, m, H, T.u);
     rowgemm(T.u, H, H, m, T.o2, d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s);
   }
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
@@ -728,14 +734,14 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   const float* hT = T.hck + (size_t)It * T.nmax * H;
   const float* eT = T.eck + (size_t)It * T.cap_f * H;
   // output head
-  wgrad(T, T.u, H, nullptr, nullptr, nullptr, 0, H, true, d_dlogits, 1, 1, m, G + T.out[1].w, s);
+  wgrad(T, T.u, H, nullptr, nullptr, nullptr, 0, 0, H, true, d_dlogits, 1, 1, m, G + T.out[1].w, s);
   float* du = T.dpre1;
   ew(outgrad_kernel, m * H, s, d_dlogits, c->gnn.out_2.w, T.u, m, H, du);
   segsum(du, H, g.rowptr, g.rowidx, nullptr, nullptr, nn, T.dP, 2 * H, s);
   segsum(du, H, g.cscptr, g.cscidx, nullptr, nullptr, nn, T.dP + H, 2 * H, s);
-  wgrad(T, hT, H, nullptr, nullptr, nullptr, 0, H, false, T.dP, 2 * H, H, n, G + T.out[0].w, s);
-  wgrad(T, hT, H, nullptr, nullptr, nullptr, 0, H, false, T.dP + H, 2 * H, H, n, G + T.out[0].w + (size_t)H * H, s);
-  wgrad(T, eT, H, nullptr, nullptr, nullptr, 0, H, true, du, H, H, m, G + T.out[0].w + (size_t)2 * H * H, s);
+  wgrad(T, hT, H, nullptr, nullptr, nullptr, 0, 0, H, false, T.dP, 2 * H, H, n, G + T.out[0].w, s);
+  wgrad(T, hT, H, nullptr, nullptr, nullptr, 0, 0, H, false, T.dP + H, 2 * H, H, n, G + T.out[0].w + (size_t)H * H, s);
+  wgrad(T, eT, H, nullptr, nullptr, nullptr, 0, 0, H, true, du, H, H, m, G + T.out[0].w + (size_t)2 * H * H, s);
   float* dh = T.dh;
   float* dh2 = T.dh2;
   rowgemm(T.dP, 2 * H, 2 * H, n, T.oabT, dh, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
@@ -747,7 +753,7 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
     // recompute this iteration's internals from (h^{t-1}, e^{t-1})
     rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
     rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
-    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, m, H, T.t1);
+    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
     rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
     segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
     ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
@@ -755,22 +761,22 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
     rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
     // node update h^t = h + phi_v([h, msg])
     ew(dtanh_kernel, n * H, s, dh, T.q2, n * H, T.dq);
-    wgrad(T, T.q1, H, nullptr, nullptr, nullptr, 0, H, true, T.dq, H, H, n, G + T.nn[1].w, s);
+    wgrad(T, T.q1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dq, H, H, n, G + T.nn[1].w, s);
     rowgemm(T.dq, H, H, n, T.n2T, T.dq1, H, H, EPI_DTANH, T.q1, H, c->n_cu, s);
-    wgrad(T, T.nin, 2 * H, nullptr, nullptr, nullptr, 0, 2 * H, true, T.dq1, H, H, n, G + T.nn[0].w, s);
+    wgrad(T, T.nin, 2 * H, nullptr, nullptr, nullptr, 0, 0, 2 * H, true, T.dq1, H, H, n, G + T.nn[0].w, s);
     rowgemm(T.dq1, H, H, n, T.n1T, T.dnin, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
     ew(add_cols_kernel, n * H, s, dh, T.dnin, 2 * H, n, H, dh2);
     // messages: de^t += dmsg[src] + dmsg[dst]
-    if (m > 0) ew(gather_add_kernel, m * H, s, T.dnin + H, 2 * H, d_src, d_dst, m, H, T.de);
+    if (m > 0) ew(gather_add_kernel, m * H, s, T.dnin + H, 2 * H, d_src, d_dst, nn, m, H, T.de);
     // edge update e^t = e + phi_e([h_s, h_t, e])
     ew(dtanh_kernel, m * H, s, T.de, T.v, m * H, T.dpre);
-    wgrad(T, T.t1, H, nullptr, nullptr, nullptr, 0, H, true, T.dpre, H, H, m, G + T.en[1].w, s);
+    wgrad(T, T.t1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dpre, H, H, m, G + T.en[1].w, s);
     rowgemm(T.dpre, H, H, m, T.e2T, T.dpre1, H, H, EPI_DTANH, T.t1, H, c->n_cu, s);
-    wgrad(T, e, H, nullptr, nullptr, nullptr, 0, H, true, T.dpre1, H, H, m, G + T.en[0].w + (size_t)2 * H * H, s);
+    wgrad(T, e, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dpre1, H, H, m, G + T.en[0].w + (size_t)2 * H * H, s);
     segsum(T.dpre1, H, g.rowptr, g.rowidx, nullptr, nullptr, nn, T.dP, 2 * H, s);
     segsum(T.dpre1, H, g.cscptr, g.cscidx, nullptr, nullptr, nn, T.dP + H, 2 * H, s);
-    wgrad(T, h, H, nullptr, nullptr, nullptr, 0, H, false, T.dP, 2 * H, H, n, G + T.en[0].w, s);
-    wgrad(T, h, H, nullptr, nullptr, nullptr, 0, H, false, T.dP + H, 2 * H, H, n, G + T.en[0].w + (size_t)H * H, s);
+    wgrad(T, h, H, nullptr, nullptr, nullptr, 0, 0, H, false, T.dP, 2 * H, H, n, G + T.en[0].w, s);
+    wgrad(T, h, H, nullptr, nullptr, nullptr, 0, 0, H, false, T.dP + H, 2 * H, H, n, G + T.en[0].w + (size_t)H * H, s);
     rowgemm(T.dpre1, H, H, m, T.ecT, T.de, H, H, EPI_ACC, nullptr, 0, c->n_cu, s);
     rowgemm(T.dP, 2 * H, 2 * H, n, T.eabT, dh2, H, H, EPI_ACC, nullptr, 0, c->n_cu, s);
     std::swap(dh, dh2);
@@ -778,14 +784,14 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   // encoders
   if (m > 0) {
     ew(dtanh_kernel, m * H, s, T.de, T.eck, m * H, T.dpre);
-    wgrad(T, T.ea1, H, nullptr, nullptr, nullptr, 0, H, true, T.dpre, H, H, m, G + T.ee[1].w, s);
+    wgrad(T, T.ea1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dpre, H, H, m, G + T.ee[1].w, s);
     rowgemm(T.dpre, H, H, m, T.ee2T, T.dpre1, H, H, EPI_DTANH, T.ea1, H, c->n_cu, s);
-    wgrad(T, T.x6, 6, nullptr, nullptr, nullptr, 0, 6, true, T.dpre1, H, H, m, G + T.ee[0].w, s);
+    wgrad(T, T.x6, 6, nullptr, nullptr, nullptr, 0, 0, 6, true, T.dpre1, H, H, m, G + T.ee[0].w, s);
   }
   ew(dtanh_kernel, n * H, s, dh, T.hck, n * H, T.dq);
-  wgrad(T, T.na1, H, nullptr, nullptr, nullptr, 0, H, true, T.dq, H, H, n, G + T.ne[1].w, s);
+  wgrad(T, T.na1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dq, H, H, n, G + T.ne[1].w, s);
   rowgemm(T.dq, H, H, n, T.ne2T, T.dq1, H, H, EPI_DTANH, T.na1, H, c->n_cu, s);
-  wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 3, true, T.dq1, H, H, n, G + T.ne[0].w, s);
+  wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 0, 3, true, T.dq1, H, H, n, G + T.ne[0].w, s);
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
 }
 
