@@ -12,23 +12,25 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // Elementwise functions.  tanh and the logistic function are evaluated from
-// the hardware base-2 exponential (v_exp_f32) with the identities
-//   tanh(x) = sign(x) * (1 - 2 / (exp(2|x|) + 1)),   sigma(z) = 1 / (1 + exp(-z)),
+// the hardware base-2 exponential (v_exp_f32) and reciprocal (v_rcp_f32) with the
+// identities tanh(x) = 1 - 2 / (exp(2x) + 1) and sigma(z) = 1 / (1 + exp(-z)),
 // whose absolute error is a few float32 ulps of 1.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float trk_exp(float x) {
   return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }
 
+// tanh(x) = 1 - 2 / (exp(2x) + 1) on x clamped to [-9, 9] (tanh(9) rounds to 1 in
+// float32 within 3e-8): one exponential, one reciprocal, no sign handling.
 __device__ __forceinline__ float trk_tanh(float x) {
-  float ax = fminf(fabsf(x), 15.0f);
-  float t = 1.0f - 2.0f / (trk_exp(2.0f * ax) + 1.0f);
-  return copysignf(t, x);
+  x = __builtin_amdgcn_fmed3f(x, -9.0f, 9.0f);
+  const float t = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // exp(2x)
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(t + 1.0f), 1.0f);
 }
 
 __device__ __forceinline__ float trk_sigmoid(float z) {
-  z = fmaxf(fminf(z, 80.0f), -80.0f);
-  return 1.0f / (1.0f + trk_exp(-z));
+  z = __builtin_amdgcn_fmed3f(z, -80.0f, 80.0f);
+  return __builtin_amdgcn_rcpf(1.0f + trk_exp(-z));
 }
 
 // float <-> bf16, round to nearest even

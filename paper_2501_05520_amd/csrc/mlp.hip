@@ -8,6 +8,7 @@
 // memory, so a kernel can be chained behind one that produced its row count.
 #include "kernels.h"
 #include "mfma_tile.h"
+#include <stdlib.h>
 
 namespace {
 
@@ -187,15 +188,29 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
   filter_kernel<P, W, MT, NW><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
 }
 
+// Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile),
+// 1 = two independent 4-wave workgroups per CU (half the rows each, so one group's
+// epilogue overlaps the other's matrix products).
+int tile_variant() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("TRK_MLP_TILE");
+    v = e ? atoi(e) : 1;
+  }
+  return v;
+}
+
 }  // namespace
 
 int launch_embed(int prec, int W, const float* x, int n, const DevLayer& l_in, const LayerList& hid,
                  const DevLayer& l_out, int D, float* emb, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 1024) { launch_embed_t<PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecF32, 1024, 16, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
     if (W == 64) { launch_embed_t<PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   } else {
-    if (W == 1024) { launch_embed_t<PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecBF16, 1024, 32, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
     if (W == 64) { launch_embed_t<PrecBF16, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   }
   return -1;
@@ -205,10 +220,12 @@ int launch_filter(int prec, int W, const float* emb, int D, const int* src, cons
                   const int* d_m, int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out,
                   float* scores, int n_nodes, int* d_err, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 512) { launch_filter_t<PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 64) { launch_filter_t<PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   } else {
-    if (W == 512) { launch_filter_t<PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecBF16, 512, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 64) { launch_filter_t<PrecBF16, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   }
   return -1;
