@@ -36,6 +36,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
     p.add_argument("--serve-seconds", type=float, default=6.0, help="0 skips the serving measurement")
+    p.add_argument("--train-steps", type=int, default=3, help="0 skips the training-step measurement")
     return p.parse_args()
 
 
@@ -153,6 +154,41 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
             "slots": 3, "clients": n_clients, "mix_mu": list(SERVE_MUS)}
 
 
+def train_measure(cfg, nets, steps, torch, trk):
+    """Training configuration: filter + interaction network on a fresh pile-up-200
+    event per step (seeds 10000+step), BCE on generator truth, hand-written
+    backward with per-iteration recomputation, Adam; edge sets from the FP32
+    inference path.  Reports the step time and the device memory the training
+    context holds (from the driver's free-memory counter)."""
+    from gen import generate_event
+    from paper_2501_05520_amd.training import TrainContext, train_step, edge_truth
+    pipe = trk.Pipeline(cfg, nets, "fp32", max_hits=120000)
+    free0 = torch.cuda.mem_get_info()[0]
+    tc = TrainContext(cfg, nets, max_hits=120000, max_cand_edges=4_500_000, max_kept_edges=2_000_000)
+    held = free0 - torch.cuda.mem_get_info()[0]
+    times, losses = [], []
+    for k in range(steps + 1):
+        ev = generate_event(10000 + k, cfg.n_collisions)
+        emb = pipe.embed(ev.x)
+        cs, cd, _ = pipe.build_graph(emb, cap=4_500_000)
+        _, fs, fd = pipe.filter(emb, cs, cd, cap=2_000_000)
+        x = torch.as_tensor(ev.x).cuda()
+        yc = torch.as_tensor(edge_truth(ev.pid, cs.cpu().numpy(), cd.cpu().numpy())).cuda()
+        yf = torch.as_tensor(edge_truth(ev.pid, fs.cpu().numpy(), fd.cpu().numpy())).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lf, lg = train_step(tc, x, emb, (cs, cd), (fs, fd), yc, yf, lr=1e-3)
+        torch.cuda.synchronize()
+        if k > 0:                      # the first step includes one-time warm-up
+            times.append(time.perf_counter() - t0)
+        losses.append(round(lf + lg, 5))
+    tc.close()
+    pipe.close()
+    return {"steps": steps, "step_ms": round(float(np.mean(times)) * 1e3, 2) if times else None,
+            "loss": losses, "n_cand_edges": int(cs.numel()), "n_filt_edges": int(fs.numel()),
+            "device_memory_gb": round(held / 2**30, 2), "precision": "fp32 (activations and master weights)"}
+
+
 def cpu_baseline(cfg, nets, x):
     """FP64 oracle on a bounded sample of one event, scaled to events/s:
     embedding on 1/8 of the hits, the radius graph in full, the filter on 1/16
@@ -254,7 +290,15 @@ def main():
             "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
         }
     if args.serve_seconds > 0:
-        result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)
+        try:
+            result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)
+        except trk.TrkError as e:
+            result["serving"] = {"error": str(e)}
+    if args.train_steps > 0:
+        try:
+            result["training"] = train_measure(cfg, nets, args.train_steps, torch, trk)
+        except trk.TrkError as e:
+            result["training"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, nets, xs[0])
     print(json.dumps(result), flush=True)
