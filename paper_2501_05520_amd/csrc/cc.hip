@@ -45,6 +45,21 @@ __global__ void uf_init(int* parent, int n) {
   GRID_STRIDE(i, n) parent[i] = (int)i;
 }
 
+// Initial forest: every spacepoint points at the smallest id among itself and its
+// kept neighbours with smaller ids (parent[x] <= x, same component), which links most
+// of each component before the union pass.
+__global__ void uf_init_min(int* parent, const int* __restrict__ src, const int* __restrict__ dst,
+                            const float* __restrict__ scores, float cut, int64_t m_cap, const int* d_m, int n) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  GRID_STRIDE(e, m) {
+    if (!scores || scores[e] > cut) {
+      const int a = src[e], b = dst[e];
+      if ((unsigned)a < (unsigned)n && (unsigned)b < (unsigned)n && a != b)
+        atomicMin(&parent[a > b ? a : b], a > b ? b : a);
+    }
+  }
+}
+
 __global__ void uf_hook(int* parent, const int* __restrict__ src, const int* __restrict__ dst,
                         const float* __restrict__ scores, float cut, int64_t m_cap, const int* d_m, int n,
                         int* d_kept, int* d_err) {
@@ -87,6 +102,8 @@ void launch_components(int n, const int* src, const int* dst, const float* score
                        const int* d_m, int* labels, int* d_kept, int* d_err, hipStream_t s) {
   if (n <= 0) return;
   uf_init<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
+  if (m_cap > 0)
+    uf_init_min<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n);
   if (m_cap > 0) uf_hook<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n, d_kept, d_err);
   uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
 }

@@ -16,6 +16,7 @@
 #include "kernels.h"
 #include "mfma_tile.h"
 #include <algorithm>
+#include <stdlib.h>
 
 namespace {
 
@@ -319,11 +320,23 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
       const int* ptr = pass == 0 ? sptr : dptr;
       const int* idx = pass == 0 ? sidx : didx;
       const int b = ptr[node], end = ptr[node + 1];
-      for (int k = b + grp; k < end; k += RPS) {
-        const uint4 u = *(const uint4*)(e + (size_t)idx[k] * H + col);
-        const T* v = (const T*)&u;
+      for (int base = b; base < end; base += 64) {
+        // the next (up to) 64 edge ids in one coalesced load; rows are then fetched
+        // with independent loads, one row per lane group and step
+        const int cnt = min(64, end - base);
+        const int my = l < cnt ? idx[base + l] : 0;
+        const int steps = (cnt + RPS - 1) / RPS;   // uniform over the wave: the shuffle needs every lane
+#pragma unroll 4
+        for (int st = 0; st < steps; ++st) {
+          const int k = grp + st * RPS;
+          const int eid = __shfl(my, k < cnt ? k : 0, 64);
+          if (k < cnt) {
+            const uint4 u = *(const uint4*)(e + (size_t)eid * H + col);
+            const T* v = (const T*)&u;
 #pragma unroll
-        for (int q = 0; q < V; ++q) acc[q] += (float)v[q];
+            for (int q = 0; q < V; ++q) acc[q] += (float)v[q];
+          }
+        }
       }
     }
     // combine the row groups: lanes with the same column, fixed butterfly order
@@ -427,34 +440,52 @@ __global__ void incidence_fill(const int* __restrict__ key, int64_t m_cap, const
   }
 }
 
-template <class P, int H, int MT, int NW>
+template <class P, int H, int MTE, int MTN, int NW>
 void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap, const int* d_m,
              float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
   typedef typename P::act_t T;
   T* proj = (T*)g.proj;
   T* e = (T*)g.e;
   launch_incidence(src, dst, m_cap, d_m, n, g, s);
-  const int ngrid = (int)std::min<int64_t>((n + MT - 1) / MT, (int64_t)n_cu * 4);
-  const int64_t etiles = (m_cap + MT - 1) / MT;
-  const int egrid = (int)std::min<int64_t>(etiles, (int64_t)n_cu * 4);
+  const int ngrid = (int)std::min<int64_t>((n + MTN - 1) / MTN, (int64_t)n_cu * 8);
+  const int64_t etiles = (m_cap + MTE - 1) / MTE;
+  const int egrid = (int)std::min<int64_t>(etiles, (int64_t)n_cu * 8);
   const DevLayer& first_proj = net.iters > 0 ? net.edge_ab : net.out_ab;
   if (ngrid > 0)
-    node_encode_kernel<P, H, MT, NW><<<ngrid, NW * 64, 0, s>>>(x, n, net.node_enc1, net.node_enc2, first_proj, g.h, proj);
+    node_encode_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(x, n, net.node_enc1, net.node_enc2, first_proj, g.h, proj);
   if (egrid > 0)
-    edge_encode_kernel<P, H, MT, NW><<<egrid, NW * 64, 0, s>>>(x, n, src, dst, m_cap, d_m, net.edge_enc1,
-                                                               net.edge_enc2, e, d_err);
+    edge_encode_kernel<P, H, MTE, NW><<<egrid, NW * 64, 0, s>>>(x, n, src, dst, m_cap, d_m, net.edge_enc1,
+                                                                net.edge_enc2, e, d_err);
   for (int it = 0; it < net.iters; ++it) {
     if (egrid > 0)
-      edge_kernel<P, H, MT, NW, false><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
-                                                                 net.edge_2, net.out_2, nullptr);
+      edge_kernel<P, H, MTE, NW, false><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
+                                                                  net.edge_2, net.out_2, nullptr);
     const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
     aggregate_kernel<P, H><<<blocks_for(n, 4, 16384), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
     if (ngrid > 0)
-      node_step_kernel<P, H, MT, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
+      node_step_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
   }
   if (egrid > 0)
-    edge_kernel<P, H, MT, NW, true><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,
-                                                              net.edge_2, net.out_2, scores);
+    edge_kernel<P, H, MTE, NW, true><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,
+                                                               net.edge_2, net.out_2, scores);
+}
+
+// Row tiles of the H=128 kernels (edge tile, node tile): smaller tiles use less LDS and
+// let more workgroups share a CU.
+int gnn_tile_variant() {
+  const char* e = getenv("TRK_GNN_TILE");
+  return e ? atoi(e) : 1;
+}
+
+template <class P>
+void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
+                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
+  switch (gnn_tile_variant()) {
+    case 0: run_gnn<P, 128, 64, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
+    case 2: run_gnn<P, 128, 32, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
+    case 3: run_gnn<P, 128, 32, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
+    default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
+  }
 }
 
 }  // namespace
@@ -479,11 +510,11 @@ int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* sr
                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
   if (n <= 0) return 0;
   if (prec == TRK_PREC_F32) {
-    if (net.H == 128) { run_gnn<PrecF32, 128, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
-    if (net.H == 32) { run_gnn<PrecF32, 32, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 128) { run_gnn128<PrecF32>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 32) { run_gnn<PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
   } else {
-    if (net.H == 128) { run_gnn<PrecBF16, 128, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
-    if (net.H == 32) { run_gnn<PrecBF16, 32, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 128) { run_gnn128<PrecBF16>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 32) { run_gnn<PrecBF16, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
   }
   return -1;
 }

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ p
     V[c][k] = (k < D) ? cos(0.7 * (k + 1) * (c + 1) + 0.3 * c) : 0.0;
   }
   __syncthreads();
-  for (int it = 0; it < 64; ++it) {
+  for (int it = 0; it < 24; ++it) {
     if (t < 3 * EP) {
       const int c = t / EP, k = t % EP;
       double s = 0.0;

@@ -188,14 +188,13 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
   filter_kernel<P, W, MT, NW><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
 }
 
-// Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile),
-// 1 = two independent 4-wave workgroups per CU (half the rows each, so one group's
-// epilogue overlaps the other's matrix products).
+// Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
+// the faster shape on MI355X), 1 = two 4-wave workgroups per CU with half the rows.
 int tile_variant() {
   static int v = -1;
   if (v < 0) {
     const char* e = getenv("TRK_MLP_TILE");
-    v = e ? atoi(e) : 1;
+    v = e ? atoi(e) : 0;
   }
   return v;
 }
