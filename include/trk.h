@@ -230,14 +230,19 @@ void trk_server_destroy(trk_server* srv);
  * binary cross-entropy with logits on truth labels, averaged over the candidate
  * edges (filter) and over the filtered edges (interaction network); the edge sets
  * are inputs held fixed.  Parameters live in one flat FP32 device vector: the
- * networks filter, node encoder, edge encoder, edge network, node network and
- * output head, each layer as W[fan_in][fan_out] then b[fan_out] (the weight-blob
- * order without the embedding).  Gradients use the same layout.  A *_bwd call
+ * networks filter, node encoder, edge encoder, edge network, node network,
+ * output head and embedding, each layer as W[fan_in][fan_out] then b[fan_out].  Gradients use the same layout.  A *_bwd call
  * uses the state of the preceding *_fwd call of the same context on the same
  * edges, and adds its gradients to d_grads.  The interaction-network backward
  * stores only the per-iteration node and edge states in the forward pass and
  * recomputes each iteration's internals during the backward pass.
  * ---------------------------------------------------------------------- */
+
+/* Embedding (metric learning), a reading of the paper's statement that hits of
+ * one particle end up close together in the latent space: pairs (a, b) labelled
+ * y = 1 (same particle) or 0, objective
+ *   L = mean_{y=1} d^2 + mean_{y=0} max(0, margin - d)^2,  d = |emb_a - emb_b|.
+ * The embedding layers follow the output head in the flat parameter vector. */
 
 /* Number of floats of the flat parameter (and gradient) vector. */
 int64_t trk_train_param_count(const trk_config* cfg);
@@ -261,6 +266,17 @@ int trk_gnn_train_fwd(trk_ctx* ctx, const float* d_x, int64_t n, const int32_t* 
 int trk_gnn_train_bwd(trk_ctx* ctx, const float* d_x, int64_t n, const int32_t* d_src,
                       const int32_t* d_dst, int64_t m, const float* d_dlogits, float* d_grads,
                       hipStream_t stream);
+/* Embedding d_emb[n][emb_dim] of d_x[n][3], keeping the activations. */
+int trk_embed_train_fwd(trk_ctx* ctx, const float* d_x, int64_t n, float* d_emb, hipStream_t stream);
+/* Adds dL/dparams of the embedding, given dL/demb[n][emb_dim], to d_grads. */
+int trk_embed_train_bwd(trk_ctx* ctx, const float* d_x, int64_t n, const float* d_demb, float* d_grads,
+                        hipStream_t stream);
+/* Pair objective of the embedding over npairs pairs (d_pa, d_pb, labels d_y in {0,1});
+ * writes dL/demb into d_demb[n][emb_dim] (overwritten) and, if h_loss, the loss
+ * (synchronises).  npairs <= max_cand_edges. */
+int trk_pair_loss(trk_ctx* ctx, const float* d_emb, int64_t n, const int32_t* d_pa, const int32_t* d_pb,
+                  const float* d_y, int64_t npairs, float margin, float* d_demb, float* h_loss,
+                  hipStream_t stream);
 /* Mean binary cross-entropy with logits of z[m] against targets y[m] in {0,1}:
  * writes dL/dz = (sigmoid(z) - y) / m and, if h_loss, the loss (synchronises). */
 int trk_bce_with_logits(trk_ctx* ctx, const float* d_logits, const float* d_targets, int64_t m,

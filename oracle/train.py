@@ -160,3 +160,41 @@ def train_loss_and_grad(x, pid, emb, cand, filt, nets, iters):
 
 
 TRAINED_NETS = ("filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
+
+
+# ---------------------------------------------------------------------------
+# embedding (metric learning)
+# ---------------------------------------------------------------------------
+def pair_loss_and_grad(emb, pa, pb, y, margin):
+    """Pair objective of the metric-learning embedding (a reading: the paper only
+    says that hits of one particle end up close together in the latent space):
+        L = mean over positive pairs of d^2 + mean over negative pairs of max(0, margin - d)^2
+    with d the Euclidean distance of the two embeddings.  Returns (L, dL/demb)."""
+    e = _f64(emb)
+    pa = np.asarray(pa, np.int64)
+    pb = np.asarray(pb, np.int64)
+    y = np.asarray(y) > 0.5
+    diff = e[pa] - e[pb]
+    d2 = np.einsum("ij,ij->i", diff, diff)
+    d = np.sqrt(d2)
+    npos, nneg = int(y.sum()), int((~y).sum())
+    hinge = np.maximum(0.0, margin - d)
+    loss = (d2[y].sum() / npos if npos else 0.0) + ((hinge[~y] ** 2).sum() / nneg if nneg else 0.0)
+    coef = np.zeros_like(d)
+    if npos:
+        coef[y] = 2.0 / npos
+    if nneg:
+        act = (~y) & (hinge > 0) & (d > 0)
+        coef[act] = -2.0 * hinge[act] / d[act] / nneg
+    g = coef[:, None] * diff
+    demb = np.zeros_like(e)
+    np.add.at(demb, pa, g)
+    np.add.at(demb, pb, -g)
+    return loss, demb
+
+
+def embed_loss_and_grad(x, pa, pb, y, margin, nets):
+    acts = mlp_forward(x, nets["emb"], tanh_last=False)
+    loss, demb = pair_loss_and_grad(acts[-1], pa, pb, y, margin)
+    grads, _ = mlp_backward(acts, nets["emb"], False, demb)
+    return loss, acts[-1], grads

@@ -85,13 +85,14 @@ __global__ void bias_fill_kernel(float* out, int nout, const float* b, int N) {
 // ---------------------------------------------------------------------------
 // rowgemm: out = epi(X W), X [m][K] row-major (ldx), W fragment blocks (FP32)
 // ---------------------------------------------------------------------------
-constexpr int RG_MT = 64, RG_NW = 4, RG_KMAX = 512;
+constexpr int RG_NW = 4;
 
-template <int NTW>
+template <int NTW, int RG_MT, int RG_KMAX>
 __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __restrict__ X, int ldx, int K, int64_t m,
                                                              DevLayer W, float* __restrict__ out, int ldo, int N,
                                                              int epi, const float* __restrict__ aux, int ldaux) {
   constexpr int LDX = RG_KMAX + 4;
+  constexpr int MTW = RG_MT / 16;
   __shared__ __align__(16) float xs[RG_MT * LDX];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int kpad = W.nkb * 16;
@@ -104,14 +105,14 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __rest
     }
     __syncthreads();
     for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
-      f32x4 acc[4][NTW];
+      f32x4 acc[MTW][NTW];
       acc_zero(acc);
-      tile_gemm<PrecF32, 4, NTW>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
+      tile_gemm<PrecF32, MTW, NTW>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
         const int n0 = (nt0 + j) * 16 + 4 * g;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < MTW; ++i) {
           const int64_t row = row0 + i * 16 + r;
           if (row >= m) continue;
 #pragma unroll
@@ -213,7 +214,7 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunk
 // per-node sums of rows of M [m][H] over incidence lists (src, dst or both), fixed order
 __global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __restrict__ p1, const int* __restrict__ i1,
                               const int* __restrict__ p2, const int* __restrict__ i2, int n, float* __restrict__ out,
-                              int ldo) {
+                              int ldo, float sign2) {
   const int waves = gridDim.x * (blockDim.x >> 6);
   const int l = lane_id();
   for (int node = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); node < n; node += waves) {
@@ -221,8 +222,11 @@ __global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __r
       float s = 0.f;
       if (p1)
         for (int k = p1[node]; k < p1[node + 1]; ++k) s += M[(size_t)i1[k] * H + c];
-      if (p2)
-        for (int k = p2[node]; k < p2[node + 1]; ++k) s += M[(size_t)i2[k] * H + c];
+      if (p2) {
+        float s2 = 0.f;
+        for (int k = p2[node]; k < p2[node + 1]; ++k) s2 += M[(size_t)i2[k] * H + c];
+        s += sign2 * s2;
+      }
       out[(size_t)node * ldo + c] = s;
     }
   }
@@ -328,6 +332,66 @@ __global__ void adam_kernel(float* p, const float* gr, float* mo, float* ve, int
   }
 }
 
+// pair objective: counts of positive / negative pairs (block partials)
+__global__ __launch_bounds__(256) void pair_count_kernel(const float* y, int64_t P, int* part) {
+  __shared__ int sh[256];
+  int c = 0;
+  GRID_STRIDE(i, P) c += y[i] > 0.5f ? 1 : 0;
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void pair_count_sum_kernel(const int* part, int nb, int64_t P, int* counts) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int s = 0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    counts[0] = s;
+    counts[1] = (int)(P - s);
+  }
+}
+// per pair: g = coef * (e[a] - e[b]) with coef = 2/npos (positive) or
+// -2 max(0, margin - d) / d / nneg (negative); block partial sums of the loss
+__global__ __launch_bounds__(256) void pair_grad_kernel(const float* __restrict__ emb, int D, int n,
+                                                        const int* __restrict__ pa, const int* __restrict__ pb,
+                                                        const float* __restrict__ y, int64_t P, float margin,
+                                                        const int* __restrict__ counts, float* __restrict__ g,
+                                                        float* __restrict__ part) {
+  __shared__ float sh[256];
+  const int npos = counts[0], nneg = counts[1];
+  float lsum = 0.f;
+  GRID_STRIDE(p, P) {
+    const size_t a = node_of(pa[p], n), b = node_of(pb[p], n);
+    float diff[16];
+    float d2 = 0.f;
+    for (int k = 0; k < D; ++k) {
+      diff[k] = emb[a * D + k] - emb[b * D + k];
+      d2 = fmaf(diff[k], diff[k], d2);
+    }
+    float coef = 0.f;
+    if (y[p] > 0.5f) {
+      lsum += d2 / (float)npos;
+      coef = 2.f / (float)npos;
+    } else {
+      const float d = sqrtf(d2);
+      const float h = fmaxf(0.f, margin - d);
+      lsum += h * h / (float)nneg;
+      if (h > 0.f && d > 0.f) coef = -2.f * h / d / (float)nneg;
+    }
+    for (int k = 0; k < D; ++k) g[(size_t)p * D + k] = coef * diff[k];
+  }
+  sh[threadIdx.x] = lsum;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -340,11 +404,12 @@ struct LayerOff {
 
 struct TrainState {
   int64_t n_params = 0;
-  std::vector<LayerOff> filt, ne, ee, en, nn, out;   // per network, per layer
+  std::vector<LayerOff> filt, ne, ee, en, nn, out, emb;   // per network, per layer
   // FP32 fragment blocks for the training products
   void* fmem = nullptr;
   std::vector<DevLayer> filtF;       // forward layers 0..L (last: K x 1)
   std::vector<DevLayer> filtT;       // transposed hidden layers 1..L-1 (index l -> W_l^T)
+  std::vector<DevLayer> embF, embT;  // embedding: forward 0..L, transposed 1..L
   DevLayer ne1, ne2, ee1, ee2, ec, eab, e2, n1, n2, oc, oab, o2;   // forward
   DevLayer ne2T, ee2T, ecT, eabT, e2T, n1T, n2T, ocT, oabT;        // transposed
   // buffers
@@ -358,6 +423,10 @@ struct TrainState {
   int64_t partial_floats = 0;
   float* bce_part = nullptr;
   int64_t cap_c = 0, cap_f = 0, nmax = 0;
+  // embedding training
+  float *eact = nullptr, *edel0 = nullptr, *edel1 = nullptr, *pg = nullptr;
+  int* pcounts = nullptr;
+  GnnScratch pairs;     // incidence lists of the pairs (by first and by second hit)
 };
 
 namespace {
@@ -401,6 +470,22 @@ void offsets_for(const trk_config& k, TrainState& T) {
   net(T.en, {3 * H, H, H});
   net(T.nn, {2 * H, H, H});
   net(T.out, {3 * H, H, 1});
+  {
+    std::vector<int> ed;
+    ed.push_back(3);
+    for (int i = 0; i < k.emb_layers; ++i) ed.push_back(k.emb_hidden);
+    ed.push_back(k.emb_dim);
+    for (size_t i = 0; i + 1 < ed.size(); ++i) {
+      LayerOff L;
+      L.K = ed[i];
+      L.N = ed[i + 1];
+      L.w = o;
+      o += (int64_t)L.K * L.N;
+      L.b = o;
+      o += L.N;
+      T.emb.push_back(L);
+    }
+  }
   T.n_params = o;
 }
 
@@ -447,9 +532,15 @@ MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
 template <int NTW>
 void rowgemm_t(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
                const float* aux, int ldaux, int n_cu, hipStream_t s) {
-  const int64_t tiles = (m + RG_MT - 1) / RG_MT;
-  const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
-  if (grid > 0) rowgemm_kernel<NTW><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+  if (W.nkb * 16 <= 512) {
+    const int64_t tiles = (m + 63) / 64;
+    const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
+    if (grid > 0) rowgemm_kernel<NTW, 64, 512><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+  } else {
+    const int64_t tiles = (m + 31) / 32;
+    const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
+    if (grid > 0) rowgemm_kernel<NTW, 32, 1024><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+  }
 }
 
 void rowgemm(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
@@ -475,8 +566,8 @@ void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* g
 }
 
 void segsum(const float* M, int H, const int* p1, const int* i1, const int* p2, const int* i2, int n, float* out, int ldo,
-            hipStream_t s) {
-  segsum_kernel<<<blocks_for(n, 4, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo);
+            hipStream_t s, float sign2 = 1.f) {
+  segsum_kernel<<<blocks_for(n, 4, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo, sign2);
 }
 
 template <class K, class... A>
@@ -508,6 +599,11 @@ int train_create(trk_ctx* c) {
   fa.add(T->ne2T, H, H); fa.add(T->ee2T, H, H); fa.add(T->ecT, H, H); fa.add(T->eabT, 2 * H, H);
   fa.add(T->e2T, H, H); fa.add(T->n1T, H, 2 * H); fa.add(T->n2T, H, H); fa.add(T->ocT, H, H);
   fa.add(T->oabT, 2 * H, H);
+  const int EL = k.emb_layers, EW = k.emb_hidden;
+  T->embF.resize(EL + 1);
+  T->embT.resize(EL + 1);
+  for (int i = 0; i <= EL; ++i) fa.add(T->embF[i], T->emb[i].K, T->emb[i].N);
+  for (int i = 1; i <= EL; ++i) fa.add(T->embT[i], T->emb[i].N, T->emb[i].K);
   if (hipMalloc(&T->fmem, fa.total) != hipSuccess) return TRK_E_NOMEM;
   fa.place(T->fmem);
   const int64_t CC = k.max_cand_edges, CF = k.max_kept_edges, NH = k.max_hits, It = k.gnn_iters;
@@ -531,9 +627,21 @@ int train_create(trk_ctx* c) {
   for (float** p : {&T->q1, &T->q2, &T->dh, &T->dh2, &T->dq, &T->dq1, &T->tmpN}) a.add(*p, (size_t)NH * H);
   a.add(T->dnin, (size_t)NH * 2 * H);
   a.add(T->dP, (size_t)NH * 2 * H);
-  T->partial_floats = (int64_t)16 * 513 * 512;
+  T->partial_floats = std::max<int64_t>((int64_t)16 * 513 * 512, (int64_t)8 * (EW + 1) * EW);
+  a.add(T->eact, (size_t)EL * NH * EW);
+  a.add(T->edel0, (size_t)NH * EW);
+  a.add(T->edel1, (size_t)NH * EW);
+  a.add(T->pg, (size_t)CC * k.emb_dim);
+  a.add(T->pcounts, 8);
+  a.add(T->pairs.rowptr, NH + 1);
+  a.add(T->pairs.rowidx, CC);
+  a.add(T->pairs.cscptr, NH + 1);
+  a.add(T->pairs.cscidx, CC);
+  a.add(T->pairs.raw, CC);
+  a.add(T->pairs.cnt, NH);
+  a.add(T->pairs.tmp, scan_tmp_ints(std::max<int64_t>(CC, NH + 1)));
   a.add(T->partial, (size_t)T->partial_floats);
-  a.add(T->bce_part, 8192);
+  a.add(T->bce_part, 16384);
   if (a.commit() != hipSuccess) return TRK_E_NOMEM;
   return TRK_OK;
 }
@@ -589,6 +697,14 @@ int train_set_params(trk_ctx* c, const float* P, hipStream_t s) {
   auto same = [&](DevLayer& dst, const LayerOff& o, int r0, int K, MatView B = MatView(), int mode = 0) {
     fill(dst, K, o.N * (mode == 1 ? 2 : 1), view(P, o, r0), B, mode, o.N, mode == 1 ? nullptr : P + o.b, 0, s);
   };
+  for (int i = 0; i <= c->cfg.emb_layers; ++i) {
+    const LayerOff& o = T.emb[i];
+    fill(T.embF[i], o.K, o.N, view(P, o), none, 0, 0, P + o.b, 0, s);
+    if (i >= 1) fill(T.embT[i], o.N, o.K, view(P, o, 0, 1), none, 0, 0, nullptr, 0, s);
+  }
+  same(c->emb_in, T.emb[0], 0, 3);
+  for (int i = 1; i < c->cfg.emb_layers; ++i) same(c->emb_hid.l[i - 1], T.emb[i], 0, T.emb[i].K);
+  same(c->emb_out, T.emb[c->cfg.emb_layers], 0, T.emb[c->cfg.emb_layers].K);
   same(c->filt_in, T.filt[0], 0, T.filt[0].K);
   for (int i = 1; i < L; ++i) same(c->filt_hid.l[i - 1], T.filt[i], 0, T.filt[i].K);
   DevGNN& G = c->gnn;
@@ -792,6 +908,77 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   wgrad(T, T.na1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dq, H, H, n, G + T.ne[1].w, s);
   rowgemm(T.dq, H, H, n, T.ne2T, T.dq1, H, H, EPI_DTANH, T.na1, H, c->n_cu, s);
   wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 0, 3, true, T.dq1, H, H, n, G + T.ne[0].w, s);
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_embed_train_fwd(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, hipStream_t s) {
+  if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_emb))) return TRK_E_INVAL;
+  if (n == 0) return TRK_OK;
+  TrainState& T = *c->train;
+  const int EL = c->cfg.emb_layers, EW = c->cfg.emb_hidden, D = c->cfg.emb_dim;
+  const float* a = d_x;
+  int lda = 3, K = 3;
+  for (int i = 0; i < EL; ++i) {
+    float* o = T.eact + (size_t)i * T.nmax * EW;
+    rowgemm(a, lda, K, n, T.embF[i], o, EW, EW, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    a = o;
+    lda = EW;
+    K = EW;
+  }
+  rowgemm(a, EW, EW, n, T.embF[EL], d_emb, D, D, EPI_BIAS, nullptr, 0, c->n_cu, s);
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_embed_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const float* d_demb, float* d_grads, hipStream_t s) {
+  if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || !d_grads || (n > 0 && (!d_x || !d_demb))) return TRK_E_INVAL;
+  if (n == 0) return TRK_OK;
+  TrainState& T = *c->train;
+  const int EL = c->cfg.emb_layers, EW = c->cfg.emb_hidden, D = c->cfg.emb_dim;
+  auto act = [&](int i) { return T.eact + (size_t)(i - 1) * T.nmax * EW; };   // a_i, i = 1..EL
+  // output layer: emb = a_EL W + b (linear)
+  wgrad(T, act(EL), EW, nullptr, nullptr, nullptr, 0, 0, EW, true, d_demb, D, D, n, d_grads + T.emb[EL].w, s);
+  float* del = T.edel0;
+  float* nxt = T.edel1;
+  rowgemm(d_demb, D, D, n, T.embT[EL], del, EW, EW, EPI_DTANH, act(EL), EW, c->n_cu, s);
+  for (int i = EL - 1; i >= 0; --i) {
+    if (i == 0)
+      wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 0, 3, true, del, EW, EW, n, d_grads + T.emb[0].w, s);
+    else
+      wgrad(T, act(i), EW, nullptr, nullptr, nullptr, 0, 0, EW, true, del, EW, EW, n, d_grads + T.emb[i].w, s);
+    if (i >= 1) {
+      rowgemm(del, EW, EW, n, T.embT[i], nxt, EW, EW, EPI_DTANH, act(i), EW, c->n_cu, s);
+      std::swap(del, nxt);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+}
+
+int trk_pair_loss(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_pa, const int32_t* d_pb,
+                  const float* d_y, int64_t npairs, float margin, float* d_demb, float* h_loss, hipStream_t s) {
+  if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || npairs < 0 || npairs > c->train->cap_c || !d_emb || !d_demb)
+    return TRK_E_INVAL;
+  if (npairs > 0 && (!d_pa || !d_pb || !d_y)) return TRK_E_INVAL;
+  TrainState& T = *c->train;
+  const int D = c->cfg.emb_dim;
+  const int nn = (int)n;
+  if (h_loss) *h_loss = 0.f;
+  if (npairs == 0) {
+    launch_fill_int((int*)d_demb, 0, n * D, s);
+    return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
+  }
+  const int nb = blocks_for(npairs, 256, 4096);
+  pair_count_kernel<<<nb, 256, 0, s>>>(d_y, npairs, (int*)T.bce_part);
+  pair_count_sum_kernel<<<1, 64, 0, s>>>((const int*)T.bce_part, nb, npairs, T.pcounts);
+  pair_grad_kernel<<<nb, 256, 0, s>>>(d_emb, D, nn, d_pa, d_pb, d_y, npairs, margin, T.pcounts, T.pg, T.bce_part + 4096);
+  bce_sum_kernel<<<1, 64, 0, s>>>(T.bce_part + 4096, nb, 1, T.bce_part + 12288);
+  // node gradient: + sum over pairs where the node comes first, - sum where it comes second
+  launch_incidence(d_pa, d_pb, npairs, nullptr, nn, T.pairs, s);
+  segsum(T.pg, D, T.pairs.rowptr, T.pairs.rowidx, T.pairs.cscptr, T.pairs.cscidx, nn, d_demb, D, s, -1.f);
+  if (h_loss) {
+    if (hipMemcpyAsync(h_loss, T.bce_part + 12288, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return TRK_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return TRK_E_DEVICE;
+  }
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
 }
 

@@ -23,7 +23,7 @@ EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_fil
            "trk_server_create", "trk_server_submit", "trk_server_wait", "trk_server_stats",
            "trk_server_destroy", "trk_train_param_count", "trk_train_set_params", "trk_filter_train_fwd",
            "trk_filter_train_bwd", "trk_gnn_train_fwd", "trk_gnn_train_bwd", "trk_bce_with_logits",
-           "trk_adam_update")
+           "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss")
 
 
 class TrkError(RuntimeError):
@@ -111,6 +111,9 @@ def lib():
         L.trk_gnn_train_bwd.argtypes = [P, P, I64, P, P, I64, P, P, P]
         L.trk_bce_with_logits.argtypes = [P, P, P, I64, P, ctypes.POINTER(F), P]
         L.trk_adam_update.argtypes = [P, P, P, P, P, I64, F, F, F, F, I64, P]
+        L.trk_embed_train_fwd.argtypes = [P, P, I64, P, P]
+        L.trk_embed_train_bwd.argtypes = [P, P, I64, P, P, P]
+        L.trk_pair_loss.argtypes = [P, P, I64, P, P, P, I64, F, P, ctypes.POINTER(F), P]
         L.trk_strerror.argtypes = [ctypes.c_int]
         L.trk_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -407,7 +410,7 @@ class Server:
 # ---------------------------------------------------------------------------
 # training entry points
 # ---------------------------------------------------------------------------
-TRAIN_NETS = ("filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
+TRAIN_NETS = ("filt", "node_enc", "edge_enc", "edge_net", "node_net", "out", "emb")
 
 
 def trk_train_param_count(config):
@@ -472,4 +475,20 @@ def trk_bce_with_logits(ctx, logits, targets, dlogits, stream=None):
 def trk_adam_update(ctx, params, grads, m, v, lr, beta1, beta2, eps, step, stream=None):
     _check(lib().trk_adam_update(ctx, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), float(lr),
                                  float(beta1), float(beta2), float(eps), int(step), _stream(stream)),
-           "trk_adam_update")
+           "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss")
+
+
+def trk_embed_train_fwd(ctx, x, emb, stream=None):
+    _check(lib().trk_embed_train_fwd(ctx, _ptr(x), x.shape[0], _ptr(emb), _stream(stream)), "trk_embed_train_fwd")
+
+
+def trk_embed_train_bwd(ctx, x, demb, grads, stream=None):
+    _check(lib().trk_embed_train_bwd(ctx, _ptr(x), x.shape[0], _ptr(demb), _ptr(grads), _stream(stream)),
+           "trk_embed_train_bwd")
+
+
+def trk_pair_loss(ctx, emb, pa, pb, y, margin, demb, stream=None):
+    loss = ctypes.c_float()
+    _check(lib().trk_pair_loss(ctx, _ptr(emb), emb.shape[0], _ptr(pa), _ptr(pb), _ptr(y), pa.numel(), float(margin),
+                               _ptr(demb), ctypes.byref(loss), _stream(stream)), "trk_pair_loss")
+    return loss.value

@@ -172,3 +172,55 @@ def test_training_lowers_the_loss():
     losses = [sum(train_step(tc, x, emb, cand, filt, yc, yf, lr=3e-3)) for _ in range(30)]
     tc.close()
     assert losses[-1] < 0.8 * losses[0], losses
+
+
+def _pairs(ev, rng, n_neg=2000):
+    pid = ev.pid
+    order = np.lexsort((ev.layer, pid))
+    s, t = order[:-1], order[1:]
+    same = (pid[s] == pid[t]) & (pid[s] > 0)
+    na = rng.integers(0, ev.n, n_neg)
+    nb = rng.integers(0, ev.n, n_neg)
+    keep = na != nb
+    pa = np.concatenate([s[same], na[keep]])
+    pb = np.concatenate([t[same], nb[keep]])
+    y = np.concatenate([np.ones(int(same.sum())), ((pid[na[keep]] == pid[nb[keep]]) & (pid[na[keep]] > 0))])
+    return pa, pb, y.astype(np.float32)
+
+
+@pytest.mark.parametrize("full_width", [False, True], ids=["tiny", "w1024"])
+def test_embedding_training_gradient(full_width):
+    from paper_2501_05520_amd import trk
+    from paper_2501_05520_amd.training import TrainContext
+    from gen import MU200
+    cfg = MU200.with_(gnn_iters=1) if full_width else TINY
+    nets = make_weights(cfg, 0)
+    ev = generate_event(6, 2)
+    pa, pb, y = _pairs(ev, np.random.default_rng(2))
+    margin = float(cfg.radius)
+    loss, emb_ref, grads = OT.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets)
+    tc = TrainContext(cfg, nets, max_hits=4096, max_cand_edges=20000, max_kept_edges=1000)
+    x = _dev(ev.x, torch.float32)
+    emb = torch.empty((ev.n, cfg.emb_dim), device="cuda")
+    trk.trk_embed_train_fwd(tc.ctx, x, emb)
+    e = emb.cpu().numpy()
+    assert np.max(np.abs(e - emb_ref) / np.maximum(1.0, np.abs(emb_ref))) <= 1e-5
+    demb = torch.empty_like(emb)
+    lg = trk.trk_pair_loss(tc.ctx, emb, _dev(pa, torch.int32), _dev(pb, torch.int32), _dev(y, torch.float32), margin,
+                           demb)
+    l_own, d_own = OT.pair_loss_and_grad(e.astype(np.float64), pa, pb, y, margin)
+    assert abs(lg - l_own) <= 1e-5 * max(1.0, l_own) and abs(lg - loss) <= 1e-3 * max(1.0, loss)
+    assert _rel(demb.cpu().numpy(), d_own) <= 1e-5
+    g = torch.zeros(tc.n_params, device="cuda")
+    trk.trk_embed_train_bwd(tc.ctx, x, demb, g)
+    gn = _split(g.cpu().numpy(), nets)
+    for li, (gw, gb) in enumerate(grads):
+        assert _rel(gn["emb"][li][0], gw) <= GRAD_RTOL, (li, _rel(gn["emb"][li][0], gw))
+        assert _rel(gn["emb"][li][1], gb) <= GRAD_RTOL, (li, "b")
+    assert all(np.all(w == 0) for w, _ in gn["filt"])
+    # after a parameter reload the inference embedding equals the training forward
+    tc.sync_params()
+    e2 = torch.empty_like(emb)
+    trk.trk_embed(tc.ctx, x, e2)
+    assert torch.allclose(e2, emb, rtol=0, atol=1e-5 * max(1.0, float(emb.abs().max())))
+    tc.close()

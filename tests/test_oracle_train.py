@@ -70,3 +70,57 @@ def test_no_edges_gradient_is_zero_for_edge_nets():
     loss, z, g = T.gnn_loss_and_grad(ev.x, e0, e0, np.zeros(0), nets, 2)
     assert loss == 0.0 and z.size == 0
     assert all(np.all(gw == 0) and np.all(gb == 0) for gw, gb in g["edge_net"])
+
+
+def _pairs(ev, rng, n_neg=800):
+    pid = ev.pid
+    order = np.lexsort((ev.layer, pid))
+    s = order[:-1]
+    t = order[1:]
+    same = (pid[s] == pid[t]) & (pid[s] > 0)
+    pa, pb = list(s[same]), list(t[same])
+    na = rng.integers(0, ev.n, n_neg)
+    nb = rng.integers(0, ev.n, n_neg)
+    keep = na != nb
+    pa += list(na[keep])
+    pb += list(nb[keep])
+    y = np.concatenate([np.ones(int(same.sum())), (pid[na[keep]] == pid[nb[keep]]) & (pid[na[keep]] > 0)])
+    return np.array(pa), np.array(pb), y.astype(np.float64)
+
+
+def test_pair_loss_closed_form():
+    e = np.array([[0.0, 0.0], [3.0, 4.0], [0.3, 0.4]])
+    loss, g = T.pair_loss_and_grad(e, [0, 0], [1, 2], [1.0, 0.0], margin=1.0)
+    # positive: d^2 = 25; negative: d = 0.5, hinge 0.5 -> 0.25
+    assert abs(loss - 25.25) < 1e-12
+    # d(d^2)/de0 = 2 (e0 - e1) = (-6, -8); negative: -2 * 0.5 / 0.5 * (e0 - e2) = (0.6, 0.8)
+    assert np.allclose(g[0], [-6 + 0.6, -8 + 0.8]) and np.allclose(g[1], [6, 8]) and np.allclose(g[2], [-0.6, -0.8])
+
+
+def test_embedding_gradient_matches_finite_differences():
+    cfg = TINY
+    nets = {k: [(w.astype(np.float64), b.astype(np.float64)) for w, b in v] for k, v in make_weights(cfg, 0).items()}
+    ev = generate_event(4, 1)
+    pa, pb, y = _pairs(ev, np.random.default_rng(1))
+    margin = 0.5
+    loss, emb, grads = T.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets)
+
+    def L():
+        e = oracle.mlp(ev.x, nets["emb"])
+        return T.pair_loss_and_grad(e, pa, pb, y, margin)[0]
+
+    assert abs(L() - loss) < 1e-12
+    rng = np.random.default_rng(5)
+    eps = 1e-6
+    for li, (w, b) in enumerate(nets["emb"]):
+        for arr, garr in ((w, grads[li][0]), (b, grads[li][1])):
+            flat = arr.reshape(-1)
+            for idx in rng.choice(flat.size, min(5, flat.size), replace=False):
+                old = flat[idx]
+                flat[idx] = old + eps
+                lp = L()
+                flat[idx] = old - eps
+                lm = L()
+                flat[idx] = old
+                fd = (lp - lm) / (2 * eps)
+                assert abs(fd - garr.reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (li, idx, fd)
