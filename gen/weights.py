@@ -36,3 +36,15 @@ def make_weights(cfg, seed=0):
 
 def n_params(nets):
     return sum(w.size + b.size for layers in nets.values() for (w, b) in layers)
+
+
+def load_weights(path, cfg):
+    """Weights written by paper_2501_05520_amd.train_weights (an .npz of float32
+    arrays named '<net>.<layer>.w' / '.b'), in make_weights' layout."""
+    from .configs import mlp_dims
+    z = np.load(path, allow_pickle=False)
+    nets = {}
+    for name, dims in mlp_dims(cfg):
+        nets[name] = [(z[f"{name}.{li}.w"].astype(np.float32), z[f"{name}.{li}.b"].astype(np.float32))
+                      for li in range(len(dims) - 1)]
+    return nets

@@ -117,3 +117,87 @@ def train_step(tctx, x, emb, cand, filt, y_cand, y_filt, lr=1e-3):
     (lf + lg).backward()
     tctx.adam_step(params.grad, lr)
     return float(lf), float(lg)
+
+
+# ---------------------------------------------------------------------------
+# metric learning of the embedding, then the filter and the interaction network
+# ---------------------------------------------------------------------------
+def positive_pairs(pid, layer, reach=2):
+    """Same-particle hit pairs on layers up to `reach` apart (generator truth)."""
+    pid = np.asarray(pid)
+    layer = np.asarray(layer).astype(np.int64)
+    order = np.lexsort((layer, pid))
+    pa, pb = [], []
+    for k in range(1, reach + 1):
+        s, t = order[:-k], order[k:]
+        ok = (pid[s] == pid[t]) & (pid[s] > 0)
+        pa.append(s[ok])
+        pb.append(t[ok])
+    return np.concatenate(pa), np.concatenate(pb)
+
+
+def embedding_step(tc, ev, rng, margin, lr, n_random=1.0, max_hard=2.0):
+    """One metric-learning step on event ev: positives from the truth, hard
+    negatives from the current radius graph, uniform random negatives; returns
+    (loss, true-edge fraction of the current candidate graph)."""
+    dev = tc.device
+    x = torch.as_tensor(ev.x, device=dev)
+    emb = torch.empty((ev.n, tc.cfg.emb_dim), device=dev)
+    trk.trk_embed_train_fwd(tc.ctx, x, emb)
+    cap = int(tc.config.max_cand_edges)
+    cs = torch.empty(cap, dtype=torch.int32, device=dev)
+    cd = torch.empty_like(cs)
+    try:
+        ne, _ = trk.trk_build_graph(tc.ctx, emb, cs, cd)
+    except trk.TrkError:
+        ne = 0
+    cs_h, cd_h = cs[:ne].cpu().numpy(), cd[:ne].cpu().numpy()
+    yc = edge_truth(ev.pid, cs_h, cd_h) if ne else np.zeros(0, np.float32)
+    true_frac = float(yc.mean()) if ne else 0.0
+    pa, pb = positive_pairs(ev.pid, ev.layer)
+    npos = pa.size
+    hard = np.flatnonzero(yc < 0.5)
+    if hard.size > max_hard * npos:
+        hard = rng.choice(hard, int(max_hard * npos), replace=False)
+    nr = int(n_random * npos)
+    ra = rng.integers(0, ev.n, nr)
+    rb = rng.integers(0, ev.n, nr)
+    keep = ra != rb
+    allA = np.concatenate([pa, cs_h[hard], ra[keep]])
+    allB = np.concatenate([pb, cd_h[hard], rb[keep]])
+    y = np.concatenate([np.ones(npos, np.float32), np.zeros(hard.size, np.float32),
+                        edge_truth(ev.pid, ra[keep], rb[keep])])
+    allA, allB, y = allA[:cap], allB[:cap], y[:cap]
+    A = torch.as_tensor(allA.astype(np.int32), device=dev)
+    B = torch.as_tensor(allB.astype(np.int32), device=dev)
+    Y = torch.as_tensor(y, device=dev)
+    demb = torch.empty_like(emb)
+    loss = trk.trk_pair_loss(tc.ctx, emb, A, B, Y, margin, demb)
+    grads = torch.zeros(tc.n_params, device=dev)
+    trk.trk_embed_train_bwd(tc.ctx, x, demb, grads)
+    tc.adam_step(grads, lr)
+    return loss, true_frac
+
+
+def pipeline_step(tc, ev, lr):
+    """One filter + interaction-network step on the edge sets the current
+    parameters produce for event ev (embedding frozen)."""
+    dev = tc.device
+    x = torch.as_tensor(ev.x, device=dev)
+    emb = torch.empty((ev.n, tc.cfg.emb_dim), device=dev)
+    trk.trk_embed(tc.ctx, x, emb)
+    cap = int(tc.config.max_cand_edges)
+    cs = torch.empty(cap, dtype=torch.int32, device=dev)
+    cd = torch.empty_like(cs)
+    ne, _ = trk.trk_build_graph(tc.ctx, emb, cs, cd)
+    cs, cd = cs[:ne], cd[:ne]
+    scores = torch.empty(ne, device=dev)
+    kcap = int(tc.config.max_kept_edges)
+    ks = torch.empty(max(kcap, 1), dtype=torch.int32, device=dev)
+    kd = torch.empty_like(ks)
+    nk = trk.trk_filter(tc.ctx, emb, cs, cd, scores, ks[:kcap], kd[:kcap])
+    ks, kd = ks[:nk], kd[:nk]
+    yc = torch.as_tensor(edge_truth(ev.pid, cs.cpu().numpy(), cd.cpu().numpy()), device=dev)
+    yf = torch.as_tensor(edge_truth(ev.pid, ks.cpu().numpy(), kd.cpu().numpy()), device=dev)
+    lf, lg = train_step(tc, x, emb, (cs, cd), (ks, kd), yc, yf, lr)
+    return lf, lg, float(yc.mean()) if ne else 0.0, float(yf.mean()) if nk else 0.0
