@@ -67,6 +67,8 @@ struct trk_ctx {
   GraphScratch graph;
   GnnScratch gs;
   int* host_words = nullptr;  // pinned mirror
+  int64_t* host_offs = nullptr;  // pinned staging of batch offsets [max_events + 1]
+  int* host_counts = nullptr;    // pinned per-event counts [max_events][4]
   hipEvent_t ev_stage[8] = {};
   bool timing = false;
   TrainState* train = nullptr;   // training buffers (trk_config.training != 0)

@@ -474,7 +474,7 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
 // let more workgroups share a CU.
 int gnn_tile_variant() {
   const char* e = getenv("TRK_GNN_TILE");
-  return e ? atoi(e) : 1;
+  return e ? atoi(e) : 2;
 }
 
 template <class P>

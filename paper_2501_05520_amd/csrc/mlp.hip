@@ -191,12 +191,8 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
 // Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
 // the faster shape on MI355X), 1 = two 4-wave workgroups per CU with half the rows.
 int tile_variant() {
-  static int v = -1;
-  if (v < 0) {
-    const char* e = getenv("TRK_MLP_TILE");
-    v = e ? atoi(e) : 0;
-  }
-  return v;
+  const char* e = getenv("TRK_MLP_TILE");
+  return e ? atoi(e) : 0;
 }
 
 }  // namespace

@@ -284,7 +284,10 @@ int alloc_scratch(trk_ctx* c) {
   a.add(s.cnt, NH);
   a.add(s.tmp, tmp_ints);
   if (a.commit() != hipSuccess) return TRK_E_NOMEM;
-  if (hipHostMalloc((void**)&c->host_words, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&c->host_words, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_offs, sizeof(int64_t) * ((size_t)k.max_events + 1), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&c->host_counts, sizeof(int) * 4 * (size_t)k.max_events, hipHostMallocDefault) != hipSuccess)
     return TRK_E_NOMEM;
   return TRK_OK;
 }
@@ -408,6 +411,8 @@ void trk_destroy(trk_ctx* c) {
   if (c->arena.base) hipFree(c->arena.base);
   if (c->wmem) hipFree(c->wmem);
   if (c->host_words) hipHostFree(c->host_words);
+  if (c->host_offs) hipHostFree(c->host_offs);
+  if (c->host_counts) hipHostFree(c->host_counts);
   for (int i = 0; i < 8; ++i)
     if (c->ev_stage[i]) hipEventDestroy(c->ev_stage[i]);
   delete c;
@@ -542,19 +547,45 @@ __global__ void batch_finish_kernel(const int64_t* __restrict__ offs, const int*
   GRID_STRIDE(i, n) labels[i] -= (int)offs[ev[i]];
 }
 
-__global__ void count_edges_by_event(const int* __restrict__ src, int64_t cap, const int* d_m, const int* __restrict__ ev,
-                                     int n, const float* __restrict__ scores, float cut, int* counts, int slot) {
-  const int64_t m = d_m ? clamp_count(d_m, cap) : cap;
-  GRID_STRIDE(e, m) {
-    const int s = src[e];
-    if ((unsigned)s < (unsigned)n && (!scores || scores[e] > cut)) atomicAdd(&counts[ev[s] * 4 + slot], 1);
+// first index e in [0, m) with key[e] >= v (key ascending)
+__device__ __forceinline__ int64_t lower_bound_i(const int* key, int64_t m, int64_t v) {
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key[mid] < v) lo = mid + 1; else hi = mid;
   }
+  return lo;
 }
 
-__global__ void count_saturated_by_event(const int* __restrict__ cnt, int n, int k_max, const int* __restrict__ ev,
-                                         int* counts) {
-  GRID_STRIDE(i, n) {
-    if (cnt[i] > k_max) atomicAdd(&counts[ev[i] * 4 + 3], 1);
+// Per-event counts, one block per event, no atomics: the candidate and the filtered
+// edges are sorted by source and every event owns a contiguous range of hit ids, so an
+// event's edges form one contiguous range found by binary search.
+__global__ __launch_bounds__(256) void event_counts_kernel(const int64_t* __restrict__ offs, const int* __restrict__ csrc,
+                                                           int64_t ccap, const int* d_nc, const int* __restrict__ fsrc,
+                                                           int64_t fcap, const int* d_nf, const float* __restrict__ scores,
+                                                           float cut, const int* __restrict__ cnt, int k_max,
+                                                           int* __restrict__ counts) {
+  __shared__ int sh[2][4];
+  const int b = blockIdx.x;
+  const int64_t nc = clamp_count(d_nc, ccap), nf = clamp_count(d_nf, fcap);
+  const int64_t h0 = offs[b], h1 = offs[b + 1];
+  const int64_t c0 = lower_bound_i(csrc, nc, h0), c1 = lower_bound_i(csrc, nc, h1);
+  const int64_t f0 = lower_bound_i(fsrc, nf, h0), f1 = lower_bound_i(fsrc, nf, h1);
+  int kept = 0, sat = 0;
+  for (int64_t e = f0 + threadIdx.x; e < f1; e += blockDim.x) kept += scores[e] > cut ? 1 : 0;
+  for (int64_t i = h0 + threadIdx.x; i < h1; i += blockDim.x) sat += cnt[i] > k_max ? 1 : 0;
+  kept = wave_sum(kept);
+  sat = wave_sum(sat);
+  if (lane_id() == 0) {
+    sh[0][threadIdx.x >> 6] = kept;
+    sh[1][threadIdx.x >> 6] = sat;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counts[b * 4 + 0] = (int)(c1 - c0);
+    counts[b * 4 + 1] = (int)(f1 - f0);
+    counts[b * 4 + 2] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    counts[b * 4 + 3] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
   }
 }
 
@@ -572,29 +603,25 @@ extern "C" int trk_batch(trk_ctx* c, int32_t n_events, const float* d_x, const i
   if (infos) memset(infos, 0, sizeof(trk_event_info) * n_events);
   if (n == 0) return TRK_OK;
   DeviceGuard guard(c->device);
-  if (hipMemcpyAsync(c->offs, h_offsets, sizeof(int64_t) * (n_events + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+  // staged through pinned memory so the copy is asynchronous; the stream is idle here
+  // with respect to the previous call's use of the staging buffer (that call synchronised)
+  memcpy(c->host_offs, h_offsets, sizeof(int64_t) * (n_events + 1));
+  if (hipMemcpyAsync(c->offs, c->host_offs, sizeof(int64_t) * (n_events + 1), hipMemcpyHostToDevice, s) != hipSuccess)
     return TRK_E_DEVICE;
   event_ids_kernel<<<blocks_for(n, 256), 256, 0, s>>>(c->offs, n_events, (int)n, c->ev);
   int rc = run_chain(c, d_x, (int)n, c->ev, d_labels, s);
   if (rc) return rc;
   if (infos) {
-    launch_fill_int(c->batch_counts, 0, (int64_t)n_events * 4, s);
     const trk_config& k = c->cfg;
-    const int eb = blocks_for(k.max_cand_edges, 256, 2048);
-    count_edges_by_event<<<eb, 256, 0, s>>>(c->cand_src, k.max_cand_edges, &c->graph.counters[0], c->ev, (int)n,
-                                            nullptr, 0.f, c->batch_counts, 0);
-    count_edges_by_event<<<eb, 256, 0, s>>>(c->filt_src, k.max_kept_edges, &c->dev_words[1], c->ev, (int)n, nullptr,
-                                            0.f, c->batch_counts, 1);
-    count_edges_by_event<<<eb, 256, 0, s>>>(c->filt_src, k.max_kept_edges, &c->dev_words[1], c->ev, (int)n,
-                                            c->gnn_scores, k.score_cut, c->batch_counts, 2);
-    count_saturated_by_event<<<blocks_for(n, 256), 256, 0, s>>>(c->graph.cnt, (int)n, k.k_max, c->ev,
-                                                                 c->batch_counts);
+    event_counts_kernel<<<n_events, 256, 0, s>>>(c->offs, c->cand_src, k.max_cand_edges, &c->graph.counters[0],
+                                                 c->filt_src, k.max_kept_edges, &c->dev_words[1], c->gnn_scores,
+                                                 k.score_cut, c->graph.cnt, k.k_max, c->batch_counts);
   }
   batch_finish_kernel<<<blocks_for(n, 256), 256, 0, s>>>(c->offs, c->ev, (int)n, d_labels);
   if (check_launch()) return TRK_E_DEVICE;
-  std::vector<int> counts(infos ? (size_t)n_events * 4 : 0);
-  if (infos && hipMemcpyAsync(counts.data(), c->batch_counts, counts.size() * sizeof(int), hipMemcpyDeviceToHost, s) !=
-                   hipSuccess)
+  const int* counts = c->host_counts;
+  if (infos && hipMemcpyAsync(c->host_counts, c->batch_counts, (size_t)n_events * 4 * sizeof(int),
+                              hipMemcpyDeviceToHost, s) != hipSuccess)
     return TRK_E_DEVICE;
   if (sync_words(c, s)) return TRK_E_DEVICE;
   const int64_t n_cand = (uint32_t)c->host_words[16];

@@ -475,7 +475,7 @@ def trk_bce_with_logits(ctx, logits, targets, dlogits, stream=None):
 def trk_adam_update(ctx, params, grads, m, v, lr, beta1, beta2, eps, step, stream=None):
     _check(lib().trk_adam_update(ctx, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), float(lr),
                                  float(beta1), float(beta2), float(eps), int(step), _stream(stream)),
-           "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss")
+           "trk_adam_update")
 
 
 def trk_embed_train_fwd(ctx, x, emb, stream=None):

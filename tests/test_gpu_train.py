@@ -216,7 +216,12 @@ def test_embedding_training_gradient(full_width):
     gn = _split(g.cpu().numpy(), nets)
     for li, (gw, gb) in enumerate(grads):
         assert _rel(gn["emb"][li][0], gw) <= GRAD_RTOL, (li, _rel(gn["emb"][li][0], gw))
-        assert _rel(gn["emb"][li][1], gb) <= GRAD_RTOL, (li, "b")
+        if li == len(grads) - 1:
+            # the pair objective is translation invariant: the output bias gradient is
+            # exactly zero, so compare against the scale of the weight gradient
+            assert np.abs(gn["emb"][li][1]).max() <= 1e-5 * np.abs(gw).max()
+        else:
+            assert _rel(gn["emb"][li][1], gb) <= GRAD_RTOL, (li, "b")
     assert all(np.all(w == 0) for w, _ in gn["filt"])
     # after a parameter reload the inference embedding equals the training forward
     tc.sync_params()
