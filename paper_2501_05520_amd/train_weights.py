@@ -38,15 +38,15 @@ def main():
     cfg = CONFIGS[a.config]
     nets = make_weights(cfg, 0)
     n_max = 60 * a.mu * 12 + 1000
-    tc = TrainContext(cfg, nets, max_hits=n_max, max_cand_edges=n_max * 64, max_kept_edges=n_max * 32)
+    tc = TrainContext(cfg, nets, max_hits=n_max, max_cand_edges=n_max * cfg.k_max, max_kept_edges=n_max * 64)
     rng = np.random.default_rng(a.seed)
     log = []
     t0 = time.time()
     for k in range(a.emb_steps):
         ev = generate_event(a.seed + k, a.mu)
-        loss, frac = embedding_step(tc, ev, rng, float(cfg.radius), a.lr)
+        loss, frac, ncand = embedding_step(tc, ev, rng, float(cfg.radius), a.lr)
         if k % 20 == 0 or k == a.emb_steps - 1:
-            log.append({"phase": "embedding", "step": k, "loss": loss, "true_frac_cand": frac})
+            log.append({"phase": "embedding", "step": k, "loss": loss, "true_frac_cand": frac, "n_cand": ncand})
             print(json.dumps(log[-1]), flush=True)
     for k in range(a.pipe_steps):
         ev = generate_event(a.seed + a.emb_steps + k, a.mu)

@@ -136,10 +136,10 @@ def positive_pairs(pid, layer, reach=2):
     return np.concatenate(pa), np.concatenate(pb)
 
 
-def embedding_step(tc, ev, rng, margin, lr, n_random=1.0, max_hard=2.0):
+def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0):
     """One metric-learning step on event ev: positives from the truth, hard
     negatives from the current radius graph, uniform random negatives; returns
-    (loss, true-edge fraction of the current candidate graph)."""
+    (loss, true-edge fraction of the current candidate graph, its edge count)."""
     dev = tc.device
     x = torch.as_tensor(ev.x, device=dev)
     emb = torch.empty((ev.n, tc.cfg.emb_dim), device=dev)
@@ -176,7 +176,7 @@ def embedding_step(tc, ev, rng, margin, lr, n_random=1.0, max_hard=2.0):
     grads = torch.zeros(tc.n_params, device=dev)
     trk.trk_embed_train_bwd(tc.ctx, x, demb, grads)
     tc.adam_step(grads, lr)
-    return loss, true_frac
+    return loss, true_frac, int(ne)
 
 
 def pipeline_step(tc, ev, lr):
