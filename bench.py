@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
     p.add_argument("--serve-seconds", type=float, default=6.0, help="0 skips the serving measurement")
     p.add_argument("--train-steps", type=int, default=3, help="0 skips the training-step measurement")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 256 MiB device-to-device copy (to scale HBM counters)")
     return p.parse_args()
 
 
@@ -242,6 +244,14 @@ def main():
     evs = [generate_event(s, cfg.n_collisions) for s in EVENT_SEEDS[: args.events]]
     xs = [e.x for e in evs]
 
+    if args.copy_calibration:
+        # a plain copy of known size: the hardware byte counters of this dispatch give the
+        # factor between counter units and bytes moved
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     wall, lat, infos, labels = run_precision(args.precision, cfg, nets, xs, args.steps, args.warmup, torch, trk)
     st = stage_means(infos)
     n_cand = float(np.mean([i["n_cand_edges"] for i in infos]))
