@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 FILTER_FLOP_PER_EDGE = 2 * (2 * 512 * 512 + 512)     # hidden 512x512 layers + output dot
 EMBED_FLOP_PER_HIT = 2 * (3 * 1024 + 2 * 1024 * 1024 + 1024 * 12)
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp8all": 5000.0}
 EVENT_SEEDS = list(range(200, 210))
 
 
@@ -31,7 +31,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "fp8all"])
     p.add_argument("--no-variant", action="store_true", help="skip the BF16 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
@@ -262,7 +262,7 @@ def main():
         "metric": "events/s and p50/p99 latency per mu=200 event; per-stage MFMA/HBM roofline %",
         "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "bf16",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3", "fp8all": "fp8-e4m3"}[args.precision],
         "data": "synthetic helical-track events (seeded), random-init weights (seed 0)",
         "config": {"workload": "mu200 event: 110000 hits, emb 3-1024x3-12, r=0.2 K=256, filter 24-512x3-1, "
                                "IN H=128 T=8, trk_event per event", "events": len(xs),
@@ -284,21 +284,23 @@ def main():
         },
     }
     if not args.no_variant:
-        other = "bf16" if args.precision == "fp32" else "fp32"
-        w2, lat2, inf2, lab2 = run_precision(other, cfg, nets, xs, args.steps, args.warmup, torch, trk)
-        agr = [agreement(a, b) for a, b in zip(labels, lab2)]
-        st2 = stage_means(inf2)
-        nc2 = float(np.mean([i["n_cand_edges"] for i in inf2]))
-        result["variant"] = {
-            "precision": other, "value": round(args.steps / w2, 3), "unit": "events/s",
-            "latency_ms": {"p50": round(float(np.percentile(lat2, 50)) * 1e3, 3),
-                           "p99": round(float(np.percentile(lat2, 99)) * 1e3, 3)},
-            "stage_ms": {k: round(v, 4) for k, v in st2.items()},
-            "filter_tflops": round(nc2 * FILTER_FLOP_PER_EDGE / (st2["filter"] * 1e-3) / 1e12, 2),
-            "hit_agreement_vs_primary": round(float(np.mean([a[0] for a in agr])), 5),
-            "candidate_jaccard_vs_primary": round(float(np.mean([a[1] for a in agr])), 5),
-            "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
-        }
+        result["variants"] = {}
+        for other in [p for p in ("fp32", "bf16", "fp8", "fp8all") if p != args.precision]:
+            w2, lat2, inf2, lab2 = run_precision(other, cfg, nets, xs, args.steps, args.warmup, torch, trk)
+            agr = [agreement(a, b) for a, b in zip(labels, lab2)]
+            st2 = stage_means(inf2)
+            nc2 = float(np.mean([i["n_cand_edges"] for i in inf2]))
+            ft2 = nc2 * FILTER_FLOP_PER_EDGE / (st2["filter"] * 1e-3) / 1e12
+            result["variants"][other] = {
+                "value": round(args.steps / w2, 3), "unit": "events/s",
+                "latency_ms": {"p50": round(float(np.percentile(lat2, 50)) * 1e3, 3),
+                               "p99": round(float(np.percentile(lat2, 99)) * 1e3, 3)},
+                "stage_ms": {k: round(v, 4) for k, v in st2.items()},
+                "filter_tflops": round(ft2, 2), "filter_frac_of_peak": round(ft2 / PEAK_TFLOPS[other], 4),
+                "hit_agreement_vs_primary": round(float(np.mean([a[0] for a in agr])), 5),
+                "candidate_jaccard_vs_primary": round(float(np.mean([a[1] for a in agr])), 5),
+                "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
+            }
     if args.serve_seconds > 0:
         try:
             result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)

@@ -57,6 +57,12 @@ typedef enum {
 typedef enum {
   TRK_FP32 = 0,  /* MLP and GNN matrix products in FP32 on MFMA */
   TRK_BF16 = 1,  /* matrix products in BF16 on MFMA, FP32 accumulation; activations stored BF16 */
+  TRK_FP8 = 2,   /* the filter MLP's hidden layers in OCP FP8 E4M3 on MFMA with FP32 accumulation:
+                  * weights with one power-of-two scale per tensor (largest |w| at most 448), tanh
+                  * activations stored with the static scale 256; its first layer, the embedding
+                  * and the interaction network run as in TRK_BF16.  Needs emb_hidden and
+                  * filt_hidden divisible by 128. */
+  TRK_FP8_ALL = 3, /* TRK_FP8 plus the embedding MLP's hidden and output layers in FP8 */
 } trk_precision;
 
 /* Model and sizing configuration, the analogue of a served model's config

@@ -41,7 +41,8 @@ struct trk_ctx {
   trk_config cfg;
   int device = 0;
   int n_cu = 256;
-  int prec = TRK_PREC_F32;
+  int prec = TRK_PREC_F32;       // filter MLP (and the interaction network unless FP8)
+  int prec_emb = TRK_PREC_F32;   // embedding MLP
   hipStream_t own_stream = nullptr;
   // weights
   void* wmem = nullptr;

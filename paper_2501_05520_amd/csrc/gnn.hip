@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
-    tile_store_tanh<P>(acc, l1.b, a1, S::LDH, wave * S::NTW);
+    tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, a1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
-    tile_store_tanh<P>(acc, l1.b, a1, S::LDH, wave * S::NTW);
+    tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, a1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, in, S::LD2, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
-    tile_store_tanh<P>(acc, l1.b, t1, S::LDH, wave * S::NTW);
+    tile_store_tanh<P>(acc, l1.b, 1.f, t1, S::LDH, wave * S::NTW);
     __syncthreads();
     acc_zero(acc);
     tile_gemm<P, S::MTW, S::NTW>(acc, t1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);

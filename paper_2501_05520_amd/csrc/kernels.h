@@ -4,7 +4,7 @@
 #include <stdint.h>
 #include "layers.h"
 
-enum { TRK_PREC_F32 = 0, TRK_PREC_BF16 = 1 };
+enum { TRK_PREC_F32 = 0, TRK_PREC_BF16 = 1, TRK_PREC_FP8 = 2 };
 // bits of the device error word
 enum { TRK_ERRBIT_CAPACITY = 1, TRK_ERRBIT_INDEX = 2 };
 

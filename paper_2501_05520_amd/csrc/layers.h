@@ -7,8 +7,9 @@
 struct DevLayer {
   int K = 0, N = 0;              // logical fan-in / fan-out
   int nkb = 0, nnt = 0;          // fragment blocks along k, 16-column tiles along n
-  const uint4* w = nullptr;      // fragment blocks in the network's precision
+  const uint4* w = nullptr;      // fragment blocks in the layer's storage precision
   const float* b = nullptr;      // bias, fp32, zero-padded to nnt * 16
+  float dq = 1.f;                // dequantisation factor of the products (1 unless FP8)
 };
 
 // A layer with a single output, evaluated as a dot product in fp32.

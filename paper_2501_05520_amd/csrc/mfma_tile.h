@@ -4,20 +4,29 @@
 // LDS.  The product is issued in transposed form, D = W^T X^T, so that the 16x16
 // accumulator of a lane holds four consecutive output columns of one row:
 //   lane l, register i  ->  row m = 16*mt + (l & 15),  column n = 16*nt + 4*(l >> 4) + i.
-// Operand fragments are 16 bytes per lane for both precisions:
-//   FP32 (v_mfma_f32_16x16x4_f32, four issues per fragment): lane group g = l>>4
-//        carries k = 16*kb + 4g + s in issue s = 0..3;
-//   BF16 (v_mfma_f32_16x16x32_bf16): lane group g carries k = 32*kb + 8g + j, j = 0..7.
+// Operand fragments per lane:
+//   FP32 (v_mfma_f32_16x16x4_f32, four issues per 16-byte fragment): lane group
+//        g = l>>4 carries k = 16*kb + 4g + s in issue s = 0..3;
+//   BF16 (v_mfma_f32_16x16x32_bf16, 16 bytes): lane group g carries k = 32*kb + 8g + j, j = 0..7;
+//   FP8  (v_mfma_scale_f32_16x16x128_f8f6f4 in E4M3 mode with unit block scales,
+//        32 bytes): lane group g carries k = 128*kb + 32g + j, j = 0..31.
 // Any assignment of k to (lane group, slot) is valid as long as the weight and the
 // activation fragments agree, which lets each lane read 16 contiguous bytes of its
 // activation row from LDS.  Weights are pre-arranged on the host into "fragment
-// blocks": block (nt, kb) of a layer is 64 lanes x 16 bytes, stored at index
-// nt * nkb + kb, so that a wave fetches one block with a single coalesced 1 KB load.
+// blocks": block (nt, kb) of a layer is 64 lanes x sizeof(fragment), stored at
+// index nt * nkb + kb, so that a wave fetches one block with coalesced loads.
+//
+// Epilogues compute tanh(acc * dq + b): dq is 1 for FP32 and BF16 layers and the
+// product of the inverse weight and activation scales for FP8 layers, so the
+// dequantisation rides on the bias addition (one FMA either way).
 #pragma once
 #include "common.h"
 
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
 struct PrecF32 {
   typedef float act_t;
+  typedef uint4 frag_t;
   static constexpr int KB = 16;          // k per fragment block
   static constexpr int PAD = 4;          // row padding in elements (16 bytes)
   static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
@@ -36,6 +45,7 @@ struct PrecF32 {
 
 struct PrecBF16 {
   typedef __bf16 act_t;
+  typedef uint4 frag_t;
   static constexpr int KB = 32;
   static constexpr int PAD = 8;
   static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
@@ -50,6 +60,36 @@ struct PrecBF16 {
   static __device__ __forceinline__ float load1(const __bf16* p) { return (float)*p; }
   static __device__ __forceinline__ __bf16 cvt(float v) { return (__bf16)v; }
 };
+
+// OCP FP8 E4M3 (max 448).  Activations are tanh outputs (|a| <= 1) stored as
+// E4M3(256 a): the static scale keeps them in the normal range down to |a| ~ 6e-5.
+// Weights carry a per-tensor power-of-two scale chosen on the host.
+struct PrecFP8 {
+  typedef uint8_t act_t;
+  typedef i32x8 frag_t;
+  static constexpr int KB = 128;
+  static constexpr int PAD = 16;
+  static constexpr float ACT_SCALE = 256.f;
+  static __device__ __forceinline__ void mma(f32x4& acc, const i32x8& w, const i32x8& x) {
+    // format 0 (E4M3) for both operands, block scales 2^(127-127) = 1
+    acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, 127);
+  }
+  static __device__ __forceinline__ void store4(uint8_t* p, float a, float b, float c, float d) {
+    int v = __builtin_amdgcn_cvt_pk_fp8_f32(a * ACT_SCALE, b * ACT_SCALE, 0, false);
+    v = __builtin_amdgcn_cvt_pk_fp8_f32(c * ACT_SCALE, d * ACT_SCALE, v, true);
+    *(int*)p = v;
+  }
+};
+
+template <class P>
+__device__ __forceinline__ typename P::frag_t load_frag(const typename P::act_t* p) {
+  if constexpr (sizeof(typename P::frag_t) == 16) {
+    return *(const uint4*)p;
+  } else {
+    const uint4 a = *(const uint4*)p, b = *(const uint4*)(p + 16);
+    return typename P::frag_t{(int)a.x, (int)a.y, (int)a.z, (int)a.w, (int)b.x, (int)b.y, (int)b.z, (int)b.w};
+  }
+}
 
 template <int MTW, int NTW>
 __device__ __forceinline__ void acc_zero(f32x4 (&acc)[MTW][NTW]) {
@@ -69,11 +109,12 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
   const int l = lane_id();
   const int g = l >> 4, r = l & 15;
   const typename P::act_t* xl = xs + r * ldx + g * (P::KB / 4);
-  const uint4* wl = wb + (size_t)nt0 * nkb * 64 + l;
+  typedef typename P::frag_t F;
+  const F* wl = (const F*)wb + (size_t)nt0 * nkb * 64 + l;
   if (nkb_run <= 0) return;
   // one weight fragment per n-tile in flight: the fragment of n-tile j for the next k
   // block is requested as soon as the current one has been consumed
-  uint4 w[NTW];
+  F w[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) w[j] = wl[((size_t)j * nkb + kb0) * 64];
   for (int kk = 0; kk < nkb_run; ++kk) {
@@ -81,9 +122,9 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
     // the last block re-reads itself so that every load is unconditional and the
     // compiler can wait for each fragment individually
     const int kbn = kk + 1 < nkb_run ? kb + 1 : kb;
-    uint4 xf[MTW];
+    F xf[MTW];
 #pragma unroll
-    for (int i = 0; i < MTW; ++i) xf[i] = *(const uint4*)(xl + i * 16 * ldx + kb * P::KB);
+    for (int i = 0; i < MTW; ++i) xf[i] = load_frag<P>(xl + i * 16 * ldx + kb * P::KB);
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
 #pragma unroll
@@ -95,10 +136,11 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
   }
 }
 
-// Epilogue: out = tanh(acc + bias) written to an LDS tile (leading dimension ldo).
+// Epilogue: out = tanh(acc * dq + bias) written to an LDS tile (leading dimension
+// ldo) in the storage format of P.
 template <class P, int MTW, int NTW>
 __device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], const float* __restrict__ bias,
-                                                typename P::act_t* out, int ldo, int nt0) {
+                                                float dq, typename P::act_t* out, int ldo, int nt0) {
   const int l = lane_id();
   const int g = l >> 4, r = l & 15;
 #pragma unroll
@@ -108,8 +150,8 @@ __device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], co
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
       const f32x4 a = acc[i][j];
-      P::store4(out + (i * 16 + r) * ldo + n, trk_tanh(a[0] + b.x), trk_tanh(a[1] + b.y),
-                trk_tanh(a[2] + b.z), trk_tanh(a[3] + b.w));
+      P::store4(out + (i * 16 + r) * ldo + n, trk_tanh(fmaf(a[0], dq, b.x)), trk_tanh(fmaf(a[1], dq, b.y)),
+                trk_tanh(fmaf(a[2], dq, b.z)), trk_tanh(fmaf(a[3], dq, b.w)));
     }
   }
 }

@@ -6,6 +6,10 @@
 // never travel to HBM.  Each wave owns a slab of output columns of every layer.
 // Tiles are walked by a persistent grid whose row count may be read from device
 // memory, so a kernel can be chained behind one that produced its row count.
+// P is the precision of the square hidden layers (and of the embedding's output
+// layer); P0 that of the narrow first layer (K = 3 or 2 * emb_dim), which is the
+// same except in FP8 mode, where the first layer runs in BF16 because an FP8
+// product consumes k in blocks of 128.
 #include "kernels.h"
 #include "mfma_tile.h"
 #include <stdlib.h>
@@ -14,29 +18,32 @@ namespace {
 
 constexpr int KIN_MAX = 32;  // widest first-layer input: [emb_s, emb_t] with emb_dim <= 16
 
-template <class P, int W, int MT, int NW>
+template <class P, class P0, int W, int MT, int NW>
 struct MlpShape {
   typedef typename P::act_t T;
+  typedef typename P0::act_t T0;
   static constexpr int LD = W + P::PAD;              // activation row stride (elements)
-  static constexpr int LDI = KIN_MAX + P::PAD;       // input row stride
+  static constexpr int LDI = KIN_MAX + P0::PAD;      // input row stride
   static constexpr int MTW = MT / 16;                // m-tiles per wave (all rows)
   static constexpr int NTW = W / 16 / NW;            // n-tiles per wave
   static constexpr int ACT_BYTES = MT * LD * (int)sizeof(T);
   static constexpr int RED_BYTES = NW * MT * 16 * 4;
   static constexpr int BUF_BYTES = ACT_BYTES > RED_BYTES ? ACT_BYTES : RED_BYTES;
   static_assert(NTW >= 1 && W % (16 * NW) == 0, "columns must split evenly over waves");
-  static_assert(BUF_BYTES + MT * LDI * (int)sizeof(T) <= 160 * 1024, "LDS budget");
+  static_assert(W % P::KB == 0, "hidden width must be a whole number of k blocks");
+  static_assert(BUF_BYTES + MT * LDI * (int)sizeof(T0) <= 160 * 1024, "LDS budget");
 };
 
 // Embedding: emb[i][0..D) = L_out(tanh(... tanh(L_in(x_i)))).
-template <class P, int W, int MT, int NW>
+template <class P, class P0, int W, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict__ x, int n, DevLayer l_in,
                                                         LayerList hid, DevLayer l_out, int D,
                                                         float* __restrict__ emb) {
-  typedef MlpShape<P, W, MT, NW> S;
+  typedef MlpShape<P, P0, W, MT, NW> S;
   typedef typename S::T T;
+  typedef typename S::T0 T0;
   __shared__ __align__(16) unsigned char buf[S::BUF_BYTES];
-  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ __align__(16) T0 xin[MT * S::LDI];
   T* act = (T*)buf;
   float* red = (float*)buf;
   const int wave = threadIdx.x >> 6;
@@ -45,22 +52,22 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
   const int ntiles = (n + MT - 1) / MT;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int row0 = t * MT;
-    for (int idx = threadIdx.x; idx < MT * P::KB; idx += blockDim.x) {
-      const int m = idx / P::KB, k = idx - m * P::KB;
+    for (int idx = threadIdx.x; idx < MT * P0::KB; idx += blockDim.x) {
+      const int m = idx / P0::KB, k = idx - m * P0::KB;
       const float v = (k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f;
-      xin[m * S::LDI + k] = P::cvt(v);
+      xin[m * S::LDI + k] = P0::cvt(v);
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
-    tile_store_tanh<P>(acc, l_in.b, act, S::LD, nt0);
+    tile_gemm<P0, S::MTW, S::NTW>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
+    tile_store_tanh<P>(acc, l_in.b, l_in.dq, act, S::LD, nt0);
     __syncthreads();
     for (int h = 0; h < hid.n; ++h) {
       acc_zero(acc);
       tile_gemm<P, S::MTW, S::NTW>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
       __syncthreads();
-      tile_store_tanh<P>(acc, hid.l[h].b, act, S::LD, nt0);
+      tile_store_tanh<P>(acc, hid.l[h].b, hid.l[h].dq, act, S::LD, nt0);
       __syncthreads();
     }
     // output layer: a single 16-column tile, its k range split over the waves
@@ -78,25 +85,26 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
     __syncthreads();
     for (int idx = threadIdx.x; idx < MT * D; idx += blockDim.x) {
       const int m = idx / D, c = idx - m * D;
-      float s = l_out.b[c];
+      float s = 0.f;
       for (int w = 0; w < NW; ++w) s += red[(w * MT + m) * 16 + c];
-      if (row0 + m < n) emb[(size_t)(row0 + m) * D + c] = s;
+      if (row0 + m < n) emb[(size_t)(row0 + m) * D + c] = fmaf(s, l_out.dq, l_out.b[c]);
     }
     __syncthreads();
   }
 }
 
 // Filter: scores[e] = sigmoid(out . tanh(L_last(... tanh(L_in([emb_src, emb_dst]))))).
-template <class P, int W, int MT, int NW>
+template <class P, class P0, int W, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict__ emb, int D,
                                                          const int* __restrict__ src, const int* __restrict__ dst,
                                                          int64_t m_host, const int* __restrict__ d_m, int64_t cap,
                                                          DevLayer l_in, LayerList hid, DevVec out,
                                                          float* __restrict__ scores, int n_nodes, int* d_err) {
-  typedef MlpShape<P, W, MT, NW> S;
+  typedef MlpShape<P, P0, W, MT, NW> S;
   typedef typename S::T T;
+  typedef typename S::T0 T0;
   __shared__ __align__(16) unsigned char buf[S::BUF_BYTES];
-  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ __align__(16) T0 xin[MT * S::LDI];
   __shared__ float zred[NW * MT];
   T* act = (T*)buf;
   const int wave = threadIdx.x >> 6;
@@ -106,7 +114,7 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
   const int64_t ntiles = (m + MT - 1) / MT;
   const int nlayers = 1 + hid.n;
   const int kin = 2 * D;
-  const int kin_pad = l_in.nkb * P::KB;
+  const int kin_pad = l_in.nkb * P0::KB;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
     for (int idx = threadIdx.x; idx < MT * kin_pad; idx += blockDim.x) {
@@ -118,7 +126,7 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
         if ((unsigned)node < (unsigned)n_nodes) v = emb[(size_t)node * D + (k < D ? k : k - D)];
         else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
       }
-      xin[mm * S::LDI + k] = P::cvt(v);
+      xin[mm * S::LDI + k] = P0::cvt(v);
     }
     __syncthreads();
     for (int layer = 0; layer < nlayers; ++layer) {
@@ -126,16 +134,17 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
       f32x4 acc[S::MTW][S::NTW];
       acc_zero(acc);
       if (layer == 0)
-        tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, L.w, L.nkb, nt0, 0, L.nkb);
+        tile_gemm<P0, S::MTW, S::NTW>(acc, xin, S::LDI, L.w, L.nkb, nt0, 0, L.nkb);
       else
         tile_gemm<P, S::MTW, S::NTW>(acc, act, S::LD, L.w, L.nkb, nt0, 0, L.nkb);
       if (layer + 1 < nlayers) {
         if (layer > 0) __syncthreads();
-        tile_store_tanh<P>(acc, L.b, act, S::LD, nt0);
+        tile_store_tanh<P>(acc, L.b, L.dq, act, S::LD, nt0);
         __syncthreads();
       } else {
         // last hidden layer: fold the single-output layer into the epilogue
         float part[S::MTW];
+        const float dq = L.dq;
 #pragma unroll
         for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
 #pragma unroll
@@ -146,8 +155,8 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
 #pragma unroll
           for (int i = 0; i < S::MTW; ++i) {
             const f32x4 a = acc[i][j];
-            part[i] += trk_tanh(a[0] + b.x) * w.x + trk_tanh(a[1] + b.y) * w.y +
-                       trk_tanh(a[2] + b.z) * w.z + trk_tanh(a[3] + b.w) * w.w;
+            part[i] += trk_tanh(fmaf(a[0], dq, b.x)) * w.x + trk_tanh(fmaf(a[1], dq, b.y)) * w.y +
+                       trk_tanh(fmaf(a[2], dq, b.z)) * w.z + trk_tanh(fmaf(a[3], dq, b.w)) * w.w;
           }
         }
 #pragma unroll
@@ -168,16 +177,16 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
   }
 }
 
-template <class P, int W, int MT, int NW>
+template <class P, class P0, int W, int MT, int NW>
 void launch_embed_t(const float* x, int n, const DevLayer& l_in, const LayerList& hid, const DevLayer& l_out,
                     int D, float* emb, int max_grid, hipStream_t s) {
   const int ntiles = (n + MT - 1) / MT;
   const int grid = ntiles < max_grid ? ntiles : max_grid;
   if (grid <= 0) return;
-  embed_kernel<P, W, MT, NW><<<grid, NW * 64, 0, s>>>(x, n, l_in, hid, l_out, D, emb);
+  embed_kernel<P, P0, W, MT, NW><<<grid, NW * 64, 0, s>>>(x, n, l_in, hid, l_out, D, emb);
 }
 
-template <class P, int W, int MT, int NW>
+template <class P, class P0, int W, int MT, int NW>
 void launch_filter_t(const float* emb, int D, const int* src, const int* dst, int64_t m_host, const int* d_m,
                      int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out, float* scores,
                      int n_nodes, int* d_err, int max_grid, hipStream_t s) {
@@ -185,11 +194,12 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
   const int64_t ntiles = (m + MT - 1) / MT;
   const int grid = (int)(ntiles < max_grid ? ntiles : max_grid);
   if (grid <= 0) return;
-  filter_kernel<P, W, MT, NW><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
+  filter_kernel<P, P0, W, MT, NW><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
 }
 
 // Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
-// the faster shape on MI355X), 1 = two 4-wave workgroups per CU with half the rows.
+// the faster shape on MI355X), 1 = two 4-wave workgroups per CU with half the rows
+// (FP8: the other row-tile height of the 8-wave workgroup).
 int tile_variant() {
   const char* e = getenv("TRK_MLP_TILE");
   return e ? atoi(e) : 0;
@@ -200,13 +210,16 @@ int tile_variant() {
 int launch_embed(int prec, int W, const float* x, int n, const DevLayer& l_in, const LayerList& hid,
                  const DevLayer& l_out, int D, float* emb, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
-    if (W == 1024) { launch_embed_t<PrecF32, 1024, 16, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
-    if (W == 64) { launch_embed_t<PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
+    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecF32, PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
+    if (W == 64) { launch_embed_t<PrecF32, PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
+  } else if (prec == TRK_PREC_FP8) {
+    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecFP8, PrecBF16, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecFP8, PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
   } else {
-    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
-    if (W == 1024) { launch_embed_t<PrecBF16, 1024, 32, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
-    if (W == 64) { launch_embed_t<PrecBF16, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
+    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecBF16, PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecBF16, PrecBF16, 1024, 32, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
+    if (W == 64) { launch_embed_t<PrecBF16, PrecBF16, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   }
   return -1;
 }
@@ -215,13 +228,16 @@ int launch_filter(int prec, int W, const float* emb, int D, const int* src, cons
                   const int* d_m, int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out,
                   float* scores, int n_nodes, int* d_err, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512) { launch_filter_t<PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
-    if (W == 64) { launch_filter_t<PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecF32, PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
+    if (W == 64) { launch_filter_t<PrecF32, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
+  } else if (prec == TRK_PREC_FP8) {
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecFP8, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
   } else {
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512) { launch_filter_t<PrecBF16, 512, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
-    if (W == 64) { launch_filter_t<PrecBF16, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecBF16, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecBF16, PrecBF16, 512, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
+    if (W == 64) { launch_filter_t<PrecBF16, PrecBF16, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   }
   return -1;
 }

@@ -6,12 +6,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "../../include/trk.h"
 #include "kernels.h"
 #include "common.h"
 #include "ctx.h"
+#include "host_quant.h"
 
 namespace {
 
@@ -32,18 +34,27 @@ uint16_t host_f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// fragment blocks of W[K][N]: block (nt, kb) at index nt * nkb + kb, 64 lanes x 16 bytes.
-std::vector<uint8_t> make_fragments(const float* w, int K, int N, int prec, int& nkb, int& nnt) {
-  const int KB = prec == TRK_PREC_F32 ? 16 : 32;
+constexpr float FP8_ACT_SCALE = 256.f;   // storage scale of FP8 activations (|tanh| <= 1)
+
+// fragment blocks of W[K][N]: block (nt, kb) at index nt * nkb + kb, 64 lanes x
+// 16 bytes (FP32, BF16) or 32 bytes (FP8, values w * scale).
+std::vector<uint8_t> make_fragments(const float* w, int K, int N, int prec, int& nkb, int& nnt, float scale = 1.f) {
+  const int KB = prec == TRK_PREC_F32 ? 16 : prec == TRK_PREC_BF16 ? 32 : 128;
+  const int FB = prec == TRK_PREC_FP8 ? 32 : 16;
   nkb = (K + KB - 1) / KB;
   nnt = (N + 15) / 16;
-  std::vector<uint8_t> out((size_t)nkb * nnt * 64 * 16, 0);
+  std::vector<uint8_t> out((size_t)nkb * nnt * 64 * FB, 0);
   for (int nt = 0; nt < nnt; ++nt)
     for (int kb = 0; kb < nkb; ++kb)
       for (int lane = 0; lane < 64; ++lane) {
         const int g = lane >> 4, r = lane & 15, n = nt * 16 + r;
-        uint8_t* dstp = out.data() + (((size_t)nt * nkb + kb) * 64 + lane) * 16;
-        if (prec == TRK_PREC_F32) {
+        uint8_t* dstp = out.data() + (((size_t)nt * nkb + kb) * 64 + lane) * FB;
+        if (prec == TRK_PREC_FP8) {
+          for (int j = 0; j < 32; ++j) {
+            const int k = kb * 128 + 32 * g + j;
+            dstp[j] = host_f2e4m3((k < K && n < N) ? w[(size_t)k * N + n] * scale : 0.f);
+          }
+        } else if (prec == TRK_PREC_F32) {
           float v[4];
           for (int s = 0; s < 4; ++s) {
             const int k = kb * 16 + 4 * g + s;
@@ -79,7 +90,8 @@ int validate_config(const trk_config* c) {
   if (!width_ok(c->filt_hidden, {64, 512}) || c->filt_layers < 1 || c->filt_layers > 7) return TRK_E_INVAL;
   if (!width_ok(c->gnn_hidden, {32, 128}) || c->gnn_iters < 0 || c->gnn_iters > 64) return TRK_E_INVAL;
   if (!(c->radius > 0.f) || c->k_max < 1 || c->k_max > 1024) return TRK_E_INVAL;
-  if (c->precision != TRK_FP32 && c->precision != TRK_BF16) return TRK_E_INVAL;
+  if (c->precision < TRK_FP32 || c->precision > TRK_FP8_ALL) return TRK_E_INVAL;
+  if (c->precision >= TRK_FP8 && (c->emb_hidden % 128 || c->filt_hidden % 128)) return TRK_E_INVAL;
   if (c->max_hits < 1 || c->max_hits > (1LL << 30)) return TRK_E_INVAL;
   if (c->max_cand_edges < 1 || c->max_cand_edges > (1LL << 31) - 1) return TRK_E_INVAL;
   if (c->max_kept_edges < 1 || c->max_kept_edges > (1LL << 31) - 1) return TRK_E_INVAL;
@@ -147,7 +159,10 @@ struct WeightUpload {
   void layer(DevLayer& D, const HostLinear& L, int prec) {
     D.K = L.K;
     D.N = L.N;
-    std::vector<uint8_t> f = make_fragments(L.w.data(), L.K, L.N, prec, D.nkb, D.nnt);
+    const float scale = prec == TRK_PREC_FP8 ? fp8_weight_scale(L.w.data(), L.w.size()) : 1.f;
+    // an FP8 layer reads FP8 activations (stored times FP8_ACT_SCALE) and FP8 weights
+    D.dq = prec == TRK_PREC_FP8 ? 1.f / (scale * FP8_ACT_SCALE) : 1.f;
+    std::vector<uint8_t> f = make_fragments(L.w.data(), L.K, L.N, prec, D.nkb, D.nnt, scale);
     std::vector<float> b((size_t)D.nnt * 16, 0.f);
     for (int n = 0; n < L.N; ++n) b[n] = L.b[n];
     const size_t wo = put(f.data(), f.size());
@@ -195,30 +210,35 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   rd.take(o1, 3 * H, H); rd.take(o2, H, 1);
   if (!rd.ok || rd.left != 0) return TRK_E_WEIGHTS;
 
-  const int prec = c->prec;
+  const int prec = c->prec, prec_emb = c->prec_emb;
+  // FP8 modes: FP8 for the layers that read a hidden activation tile of an FP8
+  // MLP, BF16 for the narrow first layers and for the whole interaction network
+  const int prec_in = prec == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec;
+  const int prec_emb_in = prec_emb == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec_emb;
+  const int prec_gnn = prec_in;
   WeightUpload up;
-  up.layer(c->emb_in, emb[0], prec);
+  up.layer(c->emb_in, emb[0], prec_emb_in);
   c->emb_hid.n = k.emb_layers - 1;
-  for (int i = 1; i < k.emb_layers; ++i) up.layer(c->emb_hid.l[i - 1], emb[i], prec);
-  up.layer(c->emb_out, emb[k.emb_layers], prec);
-  up.layer(c->filt_in, filt[0], prec);
+  for (int i = 1; i < k.emb_layers; ++i) up.layer(c->emb_hid.l[i - 1], emb[i], prec_emb);
+  up.layer(c->emb_out, emb[k.emb_layers], prec_emb);
+  up.layer(c->filt_in, filt[0], prec_in);
   c->filt_hid.n = k.filt_layers - 1;
   for (int i = 1; i < k.filt_layers; ++i) up.layer(c->filt_hid.l[i - 1], filt[i], prec);
   up.vec(c->filt_out, filt[k.filt_layers]);
   DevGNN& g = c->gnn;
   g.H = H;
   g.iters = k.gnn_iters;
-  up.layer(g.node_enc1, ne1, prec);
-  up.layer(g.node_enc2, ne2, prec);
-  up.layer(g.edge_enc1, ee1, prec);
-  up.layer(g.edge_enc2, ee2, prec);
-  up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec);
-  up.layer(g.edge_ab, side_by_side(en1, 0, H, H), prec);
-  up.layer(g.edge_2, en2, prec);
-  up.layer(g.node_1, nn1, prec);
-  up.layer(g.node_2, nn2, prec);
-  up.layer(g.out_c, rows_of(o1, 2 * H, H, true), prec);
-  up.layer(g.out_ab, side_by_side(o1, 0, H, H), prec);
+  up.layer(g.node_enc1, ne1, prec_gnn);
+  up.layer(g.node_enc2, ne2, prec_gnn);
+  up.layer(g.edge_enc1, ee1, prec_gnn);
+  up.layer(g.edge_enc2, ee2, prec_gnn);
+  up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec_gnn);
+  up.layer(g.edge_ab, side_by_side(en1, 0, H, H), prec_gnn);
+  up.layer(g.edge_2, en2, prec_gnn);
+  up.layer(g.node_1, nn1, prec_gnn);
+  up.layer(g.node_2, nn2, prec_gnn);
+  up.layer(g.out_c, rows_of(o1, 2 * H, H, true), prec_gnn);
+  up.layer(g.out_ab, side_by_side(o1, 0, H, H), prec_gnn);
   up.vec(g.out_2, o2);
   if (hipMalloc(&c->wmem, up.bytes.size()) != hipSuccess) return TRK_E_NOMEM;
   if (hipMemcpy(c->wmem, up.bytes.data(), up.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return TRK_E_DEVICE;
@@ -335,7 +355,7 @@ int run_chain(trk_ctx* c, const float* x, int n, const int* ev, int* labels, hip
   };
   launch_fill_int(c->dev_words, 0, 16, s);
   mark(0);
-  if (launch_embed(c->prec, k.emb_hidden, x, n, c->emb_in, c->emb_hid, c->emb_out, k.emb_dim, c->emb, c->n_cu, s))
+  if (launch_embed(c->prec_emb, k.emb_hidden, x, n, c->emb_in, c->emb_hid, c->emb_out, k.emb_dim, c->emb, c->n_cu, s))
     return TRK_E_INVAL;
   mark(1);
   launch_build_graph(c->emb, n, k.emb_dim, k.radius, k.k_max, ev, c->graph, c->cand_src, c->cand_dst,
@@ -386,7 +406,12 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
   trk_ctx* c = new trk_ctx();
   c->cfg = *cfg;
   c->device = device_id;
-  c->prec = cfg->precision == TRK_BF16 ? TRK_PREC_BF16 : TRK_PREC_F32;
+  switch (cfg->precision) {
+    case TRK_BF16: c->prec = c->prec_emb = TRK_PREC_BF16; break;
+    case TRK_FP8: c->prec = TRK_PREC_FP8; c->prec_emb = TRK_PREC_BF16; break;
+    case TRK_FP8_ALL: c->prec = c->prec_emb = TRK_PREC_FP8; break;
+    default: c->prec = c->prec_emb = TRK_PREC_F32;
+  }
   hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_id);
   if (c->n_cu <= 0) c->n_cu = 256;
   rc = load_weights(c, h_weights, nbytes);
@@ -422,7 +447,7 @@ int trk_embed(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, hipStream_t
   if (!c || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_emb))) return TRK_E_INVAL;
   if (n == 0) return TRK_OK;
   DeviceGuard guard(c->device);
-  if (launch_embed(c->prec, c->cfg.emb_hidden, d_x, (int)n, c->emb_in, c->emb_hid, c->emb_out, c->cfg.emb_dim, d_emb,
+  if (launch_embed(c->prec_emb, c->cfg.emb_hidden, d_x, (int)n, c->emb_in, c->emb_hid, c->emb_out, c->cfg.emb_dim, d_emb,
                    c->n_cu, s))
     return TRK_E_INVAL;
   return check_launch();

@@ -199,3 +199,53 @@ def test_bf16_error_report(nets, mid):
     print(f"bf16 vs fp64 oracle: emb max {de:.3g}; filter |dp| max {dpf.max():.3g} p99 {np.percentile(dpf, 99):.3g}; "
           f"gnn |dp| max {dq.max():.3g} p99 {np.percentile(dq, 99):.3g}; hit agreement {hit:.4f} jaccard {jac:.4f}")
     assert dpf.max() < 0.1 and dq.max() < 0.2
+
+
+# ---------------------------------------------------------------- FP8 (reported; kernel checked by emulation)
+@pytest.mark.parametrize("precision", ["fp8", "fp8all"])
+def test_fp8_error_report(nets, mid, precision):
+    from paper_2501_05520_amd.trk import Pipeline
+    ev, r = mid
+    pb = Pipeline(MU200, nets, precision, max_hits=8192)
+    e32 = r["emb"].astype(np.float32)
+    emb = pb.embed(ev.x).cpu().numpy()
+    pf = pb.filter(e32, r["src"], r["dst"])[0].cpu().numpy()
+    labels, info = pb.event(ev.x)
+    pb.close()
+    de = np.abs(emb - r["emb"])
+    dpf = np.abs(pf - r["filter_scores"])
+    hit, jac = label_agreement(labels.cpu().numpy(), r["labels"])
+    print(f"{precision} vs fp64 oracle: emb |de| max {de.max():.3g} median {np.median(de):.3g}; filter |dp| max "
+          f"{dpf.max():.3g} p99 {np.percentile(dpf, 99):.3g}; cand edges {info['n_cand_edges']} (oracle "
+          f"{r['src'].size}); hit agreement {hit:.4f} jaccard {jac:.4f}")
+    assert np.isfinite(emb).all() and np.isfinite(pf).all()
+    assert np.percentile(dpf, 50) < 0.05
+
+
+def test_fp8_matches_quantised_emulation(nets, mid):
+    from paper_2501_05520_amd.trk import Pipeline
+    from tests import quant_ref
+    ev, r = mid
+    rng = np.random.default_rng(5)
+    hits = np.sort(rng.choice(ev.n, 1024, replace=False))
+    sel = np.sort(rng.choice(r["src"].size, 4096, replace=False))
+    e32 = r["emb"].astype(np.float32)
+    pa = Pipeline(MU200, nets, "fp8all", max_hits=8192)
+    emb = pa.embed(ev.x[hits]).cpu().numpy()
+    pf = pa.filter(e32, r["src"][sel], r["dst"][sel])[0].cpu().numpy()
+    pa.close()
+    eref = quant_ref.embed_fp8(ev.x[hits], nets)
+    pref = quant_ref.filter_fp8(e32, r["src"][sel], r["dst"][sel], nets)
+    de = np.abs(emb - eref) / np.maximum(1.0, np.abs(eref))
+    dp = np.abs(pf - pref)
+    print(f"fp8 vs quantised emulation: emb rel max {de.max():.3g} median {np.median(de):.3g}; "
+          f"filter |dp| max {dp.max():.3g} median {np.median(dp):.3g}")
+    # an activation on the other side of an E4M3 rounding boundary moves a few outputs;
+    # a layout or scaling mistake would move all of them
+    assert np.median(de) < 1e-4 and np.mean(de < 2e-3) >= 0.98 and de.max() < 0.05
+    assert np.median(dp) < 1e-4 and np.mean(dp < 2e-3) >= 0.98 and dp.max() < 0.1
+    # the plain FP8 mode runs the same filter and a BF16 embedding
+    pb = Pipeline(MU200, nets, "fp8", max_hits=8192)
+    pf2 = pb.filter(e32, r["src"][sel], r["dst"][sel])[0].cpu().numpy()
+    pb.close()
+    assert np.array_equal(pf, pf2)
