@@ -277,12 +277,15 @@ int trk_embed_train_fwd(trk_ctx* ctx, const float* d_x, int64_t n, float* d_emb,
 /* Adds dL/dparams of the embedding, given dL/demb[n][emb_dim], to d_grads. */
 int trk_embed_train_bwd(trk_ctx* ctx, const float* d_x, int64_t n, const float* d_demb, float* d_grads,
                         hipStream_t stream);
-/* Pair objective of the embedding over npairs pairs (d_pa, d_pb, labels d_y in {0,1});
- * writes dL/demb into d_demb[n][emb_dim] (overwritten) and, if h_loss, the loss
- * (synchronises).  npairs <= max_cand_edges. */
+/* Pair objective of the embedding over npairs pairs (d_pa, d_pb, labels d_y in {0,1}),
+ *   L = mean over positives of d^2 + neg_weight * mean over negatives of max(0, margin - d)^2
+ * with d the distance of the two embeddings (metric learning: hits of one particle close
+ * together in the latent space, Section 2.2.2); writes dL/demb into d_demb[n][emb_dim]
+ * (overwritten) and, if h_loss, the loss (synchronises).  npairs <= max_cand_edges;
+ * margin and neg_weight >= 0, else TRK_E_INVAL. */
 int trk_pair_loss(trk_ctx* ctx, const float* d_emb, int64_t n, const int32_t* d_pa, const int32_t* d_pb,
-                  const float* d_y, int64_t npairs, float margin, float* d_demb, float* h_loss,
-                  hipStream_t stream);
+                  const float* d_y, int64_t npairs, float margin, float neg_weight, float* d_demb,
+                  float* h_loss, hipStream_t stream);
 /* Mean binary cross-entropy with logits of z[m] against targets y[m] in {0,1}:
  * writes dL/dz = (sigmoid(z) - y) / m and, if h_loss, the loss (synchronises). */
 int trk_bce_with_logits(trk_ctx* ctx, const float* d_logits, const float* d_targets, int64_t m,

@@ -165,10 +165,11 @@ TRAINED_NETS = ("filt", "node_enc", "edge_enc", "edge_net", "node_net", "out")
 # ---------------------------------------------------------------------------
 # embedding (metric learning)
 # ---------------------------------------------------------------------------
-def pair_loss_and_grad(emb, pa, pb, y, margin):
+def pair_loss_and_grad(emb, pa, pb, y, margin, neg_weight=1.0):
     """Pair objective of the metric-learning embedding (a reading: the paper only
     says that hits of one particle end up close together in the latent space):
-        L = mean over positive pairs of d^2 + mean over negative pairs of max(0, margin - d)^2
+        L = mean over positive pairs of d^2
+            + neg_weight * mean over negative pairs of max(0, margin - d)^2
     with d the Euclidean distance of the two embeddings.  Returns (L, dL/demb)."""
     e = _f64(emb)
     pa = np.asarray(pa, np.int64)
@@ -179,13 +180,13 @@ def pair_loss_and_grad(emb, pa, pb, y, margin):
     d = np.sqrt(d2)
     npos, nneg = int(y.sum()), int((~y).sum())
     hinge = np.maximum(0.0, margin - d)
-    loss = (d2[y].sum() / npos if npos else 0.0) + ((hinge[~y] ** 2).sum() / nneg if nneg else 0.0)
+    loss = (d2[y].sum() / npos if npos else 0.0) + neg_weight * ((hinge[~y] ** 2).sum() / nneg if nneg else 0.0)
     coef = np.zeros_like(d)
     if npos:
         coef[y] = 2.0 / npos
     if nneg:
         act = (~y) & (hinge > 0) & (d > 0)
-        coef[act] = -2.0 * hinge[act] / d[act] / nneg
+        coef[act] = -2.0 * neg_weight * hinge[act] / d[act] / nneg
     g = coef[:, None] * diff
     demb = np.zeros_like(e)
     np.add.at(demb, pa, g)
@@ -193,8 +194,8 @@ def pair_loss_and_grad(emb, pa, pb, y, margin):
     return loss, demb
 
 
-def embed_loss_and_grad(x, pa, pb, y, margin, nets):
+def embed_loss_and_grad(x, pa, pb, y, margin, nets, neg_weight=1.0):
     acts = mlp_forward(x, nets["emb"], tanh_last=False)
-    loss, demb = pair_loss_and_grad(acts[-1], pa, pb, y, margin)
+    loss, demb = pair_loss_and_grad(acts[-1], pa, pb, y, margin, neg_weight)
     grads, _ = mlp_backward(acts, nets["emb"], False, demb)
     return loss, acts[-1], grads

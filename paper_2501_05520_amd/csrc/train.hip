@@ -354,10 +354,11 @@ __global__ void pair_count_sum_kernel(const int* part, int nb, int64_t P, int* c
   }
 }
 // per pair: g = coef * (e[a] - e[b]) with coef = 2/npos (positive) or
-// -2 max(0, margin - d) / d / nneg (negative); block partial sums of the loss
+// -2 w max(0, margin - d) / d / nneg (negative, weight w); block partial sums of the loss
 __global__ __launch_bounds__(256) void pair_grad_kernel(const float* __restrict__ emb, int D, int n,
                                                         const int* __restrict__ pa, const int* __restrict__ pb,
                                                         const float* __restrict__ y, int64_t P, float margin,
+                                                        float neg_weight,
                                                         const int* __restrict__ counts, float* __restrict__ g,
                                                         float* __restrict__ part) {
   __shared__ float sh[256];
@@ -378,8 +379,8 @@ __global__ __launch_bounds__(256) void pair_grad_kernel(const float* __restrict_
     } else {
       const float d = sqrtf(d2);
       const float h = fmaxf(0.f, margin - d);
-      lsum += h * h / (float)nneg;
-      if (h > 0.f && d > 0.f) coef = -2.f * h / d / (float)nneg;
+      lsum += neg_weight * h * h / (float)nneg;
+      if (h > 0.f && d > 0.f) coef = -2.f * neg_weight * h / d / (float)nneg;
     }
     for (int k = 0; k < D; ++k) g[(size_t)p * D + k] = coef * diff[k];
   }
@@ -954,10 +955,12 @@ int trk_embed_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const float* d_
 }
 
 int trk_pair_loss(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_pa, const int32_t* d_pb,
-                  const float* d_y, int64_t npairs, float margin, float* d_demb, float* h_loss, hipStream_t s) {
+                  const float* d_y, int64_t npairs, float margin, float neg_weight, float* d_demb, float* h_loss,
+                  hipStream_t s) {
   if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || npairs < 0 || npairs > c->train->cap_c || !d_emb || !d_demb)
     return TRK_E_INVAL;
   if (npairs > 0 && (!d_pa || !d_pb || !d_y)) return TRK_E_INVAL;
+  if (!(neg_weight >= 0.f) || !(margin >= 0.f)) return TRK_E_INVAL;
   TrainState& T = *c->train;
   const int D = c->cfg.emb_dim;
   const int nn = (int)n;
@@ -969,7 +972,8 @@ int trk_pair_loss(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_pa
   const int nb = blocks_for(npairs, 256, 4096);
   pair_count_kernel<<<nb, 256, 0, s>>>(d_y, npairs, (int*)T.bce_part);
   pair_count_sum_kernel<<<1, 64, 0, s>>>((const int*)T.bce_part, nb, npairs, T.pcounts);
-  pair_grad_kernel<<<nb, 256, 0, s>>>(d_emb, D, nn, d_pa, d_pb, d_y, npairs, margin, T.pcounts, T.pg, T.bce_part + 4096);
+  pair_grad_kernel<<<nb, 256, 0, s>>>(d_emb, D, nn, d_pa, d_pb, d_y, npairs, margin, neg_weight, T.pcounts, T.pg,
+                                         T.bce_part + 4096);
   bce_sum_kernel<<<1, 64, 0, s>>>(T.bce_part + 4096, nb, 1, T.bce_part + 12288);
   // node gradient: + sum over pairs where the node comes first, - sum where it comes second
   launch_incidence(d_pa, d_pb, npairs, nullptr, nn, T.pairs, s);

@@ -6,7 +6,7 @@ comes from the seeded generator, the initial weights from gen.make_weights
 to floating-point reduction order.
 
   python -m paper_2501_05520_amd.train_weights --config mu200 --mu 20 \
-      --emb-steps 400 --pipe-steps 200 --out trained_mu200.npz
+      --emb-steps 600 --pipe-steps 300 --out trained_mu200.npz
 """
 import argparse
 import json
@@ -27,7 +27,9 @@ def main():
     ap.add_argument("--mu", type=int, default=20, help="pile-up of the training events")
     ap.add_argument("--emb-steps", type=int, default=400)
     ap.add_argument("--pipe-steps", type=int, default=200)
-    ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--lr", type=float, default=3e-4, help="learning rate of the filter + GNN phase")
+    ap.add_argument("--emb-lr", type=float, default=1e-3, help="learning rate of the embedding phase")
+    ap.add_argument("--neg-weight", type=float, default=10.0, help="weight of the negative-pair term")
     ap.add_argument("--seed", type=int, default=20000, help="first event seed")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -38,13 +40,13 @@ def main():
     cfg = CONFIGS[a.config]
     nets = make_weights(cfg, 0)
     n_max = 60 * a.mu * 12 + 1000
-    tc = TrainContext(cfg, nets, max_hits=n_max, max_cand_edges=n_max * cfg.k_max, max_kept_edges=n_max * 64)
+    tc = TrainContext(cfg, nets, max_hits=n_max, max_cand_edges=n_max * cfg.k_max, max_kept_edges=n_max * cfg.k_max)
     rng = np.random.default_rng(a.seed)
     log = []
     t0 = time.time()
     for k in range(a.emb_steps):
         ev = generate_event(a.seed + k, a.mu)
-        loss, frac, ncand = embedding_step(tc, ev, rng, float(cfg.radius), a.lr)
+        loss, frac, ncand = embedding_step(tc, ev, rng, float(cfg.radius), a.emb_lr, neg_weight=a.neg_weight)
         if k % 20 == 0 or k == a.emb_steps - 1:
             log.append({"phase": "embedding", "step": k, "loss": loss, "true_frac_cand": frac, "n_cand": ncand})
             print(json.dumps(log[-1]), flush=True)

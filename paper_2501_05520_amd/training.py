@@ -136,10 +136,13 @@ def positive_pairs(pid, layer, reach=2):
     return np.concatenate(pa), np.concatenate(pb)
 
 
-def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0):
+def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0, neg_weight=10.0):
     """One metric-learning step on event ev: positives from the truth, hard
-    negatives from the current radius graph, uniform random negatives; returns
-    (loss, true-edge fraction of the current candidate graph, its edge count)."""
+    negatives from the current radius graph, uniform random negatives, the
+    negative term weighted by neg_weight (without it the positive term dominates
+    and the embedding contracts: every point ends up within r of ~100 others);
+    returns (loss, true-edge fraction of the current candidate graph, its edge
+    count)."""
     dev = tc.device
     x = torch.as_tensor(ev.x, device=dev)
     emb = torch.empty((ev.n, tc.cfg.emb_dim), device=dev)
@@ -172,7 +175,7 @@ def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0):
     B = torch.as_tensor(allB.astype(np.int32), device=dev)
     Y = torch.as_tensor(y, device=dev)
     demb = torch.empty_like(emb)
-    loss = trk.trk_pair_loss(tc.ctx, emb, A, B, Y, margin, demb)
+    loss = trk.trk_pair_loss(tc.ctx, emb, A, B, Y, margin, demb, neg_weight=neg_weight)
     grads = torch.zeros(tc.n_params, device=dev)
     trk.trk_embed_train_bwd(tc.ctx, x, demb, grads)
     tc.adam_step(grads, lr)

@@ -113,7 +113,7 @@ def lib():
         L.trk_adam_update.argtypes = [P, P, P, P, P, I64, F, F, F, F, I64, P]
         L.trk_embed_train_fwd.argtypes = [P, P, I64, P, P]
         L.trk_embed_train_bwd.argtypes = [P, P, I64, P, P, P]
-        L.trk_pair_loss.argtypes = [P, P, I64, P, P, P, I64, F, P, ctypes.POINTER(F), P]
+        L.trk_pair_loss.argtypes = [P, P, I64, P, P, P, I64, F, F, P, ctypes.POINTER(F), P]
         L.trk_strerror.argtypes = [ctypes.c_int]
         L.trk_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -487,8 +487,8 @@ def trk_embed_train_bwd(ctx, x, demb, grads, stream=None):
            "trk_embed_train_bwd")
 
 
-def trk_pair_loss(ctx, emb, pa, pb, y, margin, demb, stream=None):
+def trk_pair_loss(ctx, emb, pa, pb, y, margin, demb, neg_weight=1.0, stream=None):
     loss = ctypes.c_float()
     _check(lib().trk_pair_loss(ctx, _ptr(emb), emb.shape[0], _ptr(pa), _ptr(pb), _ptr(y), pa.numel(), float(margin),
-                               _ptr(demb), ctypes.byref(loss), _stream(stream)), "trk_pair_loss")
+                               float(neg_weight), _ptr(demb), ctypes.byref(loss), _stream(stream)), "trk_pair_loss")
     return loss.value

@@ -197,8 +197,8 @@ def test_embedding_training_gradient(full_width):
     nets = make_weights(cfg, 0)
     ev = generate_event(6, 2)
     pa, pb, y = _pairs(ev, np.random.default_rng(2))
-    margin = float(cfg.radius)
-    loss, emb_ref, grads = OT.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets)
+    margin, lam = float(cfg.radius), 10.0
+    loss, emb_ref, grads = OT.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets, neg_weight=lam)
     tc = TrainContext(cfg, nets, max_hits=4096, max_cand_edges=20000, max_kept_edges=1000)
     x = _dev(ev.x, torch.float32)
     emb = torch.empty((ev.n, cfg.emb_dim), device="cuda")
@@ -207,8 +207,8 @@ def test_embedding_training_gradient(full_width):
     assert np.max(np.abs(e - emb_ref) / np.maximum(1.0, np.abs(emb_ref))) <= 1e-5
     demb = torch.empty_like(emb)
     lg = trk.trk_pair_loss(tc.ctx, emb, _dev(pa, torch.int32), _dev(pb, torch.int32), _dev(y, torch.float32), margin,
-                           demb)
-    l_own, d_own = OT.pair_loss_and_grad(e.astype(np.float64), pa, pb, y, margin)
+                           demb, neg_weight=lam)
+    l_own, d_own = OT.pair_loss_and_grad(e.astype(np.float64), pa, pb, y, margin, lam)
     assert abs(lg - l_own) <= 1e-5 * max(1.0, l_own) and abs(lg - loss) <= 1e-3 * max(1.0, loss)
     assert _rel(demb.cpu().numpy(), d_own) <= 1e-5
     g = torch.zeros(tc.n_params, device="cuda")

@@ -95,6 +95,10 @@ def test_pair_loss_closed_form():
     assert abs(loss - 25.25) < 1e-12
     # d(d^2)/de0 = 2 (e0 - e1) = (-6, -8); negative: -2 * 0.5 / 0.5 * (e0 - e2) = (0.6, 0.8)
     assert np.allclose(g[0], [-6 + 0.6, -8 + 0.8]) and np.allclose(g[1], [6, 8]) and np.allclose(g[2], [-0.6, -0.8])
+    # weight 10 on the negative term: 25 + 10 * 0.25, negative gradient scaled by 10
+    loss, g = T.pair_loss_and_grad(e, [0, 0], [1, 2], [1.0, 0.0], margin=1.0, neg_weight=10.0)
+    assert abs(loss - 27.5) < 1e-12
+    assert np.allclose(g[0], [-6 + 6.0, -8 + 8.0]) and np.allclose(g[1], [6, 8]) and np.allclose(g[2], [-6.0, -8.0])
 
 
 def test_embedding_gradient_matches_finite_differences():
@@ -102,12 +106,12 @@ def test_embedding_gradient_matches_finite_differences():
     nets = {k: [(w.astype(np.float64), b.astype(np.float64)) for w, b in v] for k, v in make_weights(cfg, 0).items()}
     ev = generate_event(4, 1)
     pa, pb, y = _pairs(ev, np.random.default_rng(1))
-    margin = 0.5
-    loss, emb, grads = T.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets)
+    margin, lam = 0.5, 3.0
+    loss, emb, grads = T.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets, neg_weight=lam)
 
     def L():
         e = oracle.mlp(ev.x, nets["emb"])
-        return T.pair_loss_and_grad(e, pa, pb, y, margin)[0]
+        return T.pair_loss_and_grad(e, pa, pb, y, margin, lam)[0]
 
     assert abs(L() - loss) < 1e-12
     rng = np.random.default_rng(5)
