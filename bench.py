@@ -85,26 +85,28 @@ def agreement(la, lb, min_hits=3):
     return hit, (len(ca & cb) / len(u) if u else 1.0)
 
 
-def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed=7, pool=6):
+def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed=7, pool=6, mus=None, rate=None):
     """Serving mix: client threads with Poisson arrivals submit events whose
-    pile-up is drawn uniformly from {50, 100, 140, 200}; one collector harvests
-    results.  First a burst measures the saturated rate, then the offered load is
-    load_frac x that rate for `seconds`.  Latency = submission -> labels on host."""
+    pile-up is drawn uniformly from `mus` (default {50, 100, 140, 200}); one
+    collector harvests results.  First a burst measures the saturated rate, then
+    the offered load is load_frac x that rate (or `rate` events/s when given) for
+    `seconds`.  Latency = submission -> labels on host."""
     import queue
     import random
     import threading
     from gen import SERVE_MUS, generate_event
-    pools = {mu: [generate_event(9000 + 97 * mu + k, mu).x for k in range(pool)] for mu in SERVE_MUS}
+    mus = list(mus or SERVE_MUS)
+    pools = {mu: [generate_event(9000 + 97 * mu + k, mu).x for k in range(pool)] for mu in mus}
     srv = trk.Server(cfg, nets, precision, n_slots=3, max_batch_events=8, max_batch_hits=330000,
                      mem_budget_bytes=64 << 30)
     # warm-up and saturated rate: a burst of 48 requests
-    burst = [pools[SERVE_MUS[k % 4]][k % pool] for k in range(48)]
+    burst = [pools[mus[k % len(mus)]][k % pool] for k in range(48)]
     t0 = time.perf_counter()
     tickets = [(srv.submit(x), x.shape[0]) for x in burst]
     for t, n in tickets:
         srv.wait(t, n)
     sat = len(burst) / (time.perf_counter() - t0)
-    rate = load_frac * sat
+    rate = load_frac * sat if rate is None else float(rate)
     done = queue.Queue()
     lat, status = [], []
     stop_at = time.perf_counter() + seconds
@@ -119,7 +121,7 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
             d = nxt - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            x = pools[rng.choice(SERVE_MUS)][rng.randrange(pool)]
+            x = pools[rng.choice(mus)][rng.randrange(pool)]
             done.put((srv.submit(x), x.shape[0]))
         done.put(None)
 
@@ -153,7 +155,7 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2)},
             "mean_batch_events": round((st["batched_events"] - st0["batched_events"]) / max(nb, 1), 2),
             "waited_for_memory": st["waited_for_memory"] - st0["waited_for_memory"],
-            "slots": 3, "clients": n_clients, "mix_mu": list(SERVE_MUS)}
+            "slots": 3, "clients": n_clients, "mix_mu": mus}
 
 
 def train_measure(cfg, nets, steps, torch, trk):
@@ -306,6 +308,16 @@ def main():
             result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)
         except trk.TrkError as e:
             result["serving"] = {"error": str(e)}
+        try:
+            # the served BF16 form on pile-up-200 events only, offered the plain FP32
+            # pipeline's own event rate: its p99 beside the FP32 p99 (host buffers,
+            # PCIe included) and its saturated rate beside the FP32 rate
+            sv = serve_load(cfg, nets, "bf16", args.serve_seconds, 1.0, trk, mus=[200], rate=value)
+            sv["vs_fp32_pipeline"] = {"fp32_events_per_s": round(value, 3),
+                                      "fp32_p99_ms": result["latency_ms"]["p99"]} if args.precision == "fp32" else None
+            result["serving_mu200"] = sv
+        except trk.TrkError as e:
+            result["serving_mu200"] = {"error": str(e)}
     if args.train_steps > 0:
         try:
             result["training"] = train_measure(cfg, nets, args.train_steps, torch, trk)

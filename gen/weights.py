@@ -48,3 +48,11 @@ def load_weights(path, cfg):
         nets[name] = [(z[f"{name}.{li}.w"].astype(np.float32), z[f"{name}.{li}.b"].astype(np.float32))
                       for li in range(len(dims) - 1)]
     return nets
+
+
+def load_trained(path, cfg):
+    """Trained weights and the configuration they were calibrated for: the .npz
+    written by paper_2501_05520_amd.train_weights carries its filter cut."""
+    z = np.load(path, allow_pickle=False)
+    cut = float(z["filter_cut"]) if "filter_cut" in z.files else float(cfg.filter_cut)
+    return cfg.with_(filter_cut=cut), load_weights(path, cfg)

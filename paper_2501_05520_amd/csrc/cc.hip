@@ -84,8 +84,8 @@ __global__ void uf_hook(int* parent, const int* __restrict__ src, const int* __r
 
 __global__ void uf_compress(int* parent, int n) {
   GRID_STRIDE(i, n) {
-    // all links were made by the previous kernel, so every value read here is an
-    // ancestor and the walk ends at the final root
+    // all links were made by earlier kernels, so every value read here is an
+    // ancestor and the walk ends at the current root
     int x = (int)i;
     int p = parent[x];
     while (p != x) {
@@ -102,8 +102,12 @@ void launch_components(int n, const int* src, const int* dst, const float* score
                        const int* d_m, int* labels, int* d_kept, int* d_err, hipStream_t s) {
   if (n <= 0) return;
   uf_init<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
-  if (m_cap > 0)
+  if (m_cap > 0) {
     uf_init_min<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n);
+    // the initial forest has chains of decreasing ids; pointing every spacepoint at
+    // the end of its chain first keeps the finds of the union pass short
+    uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
+  }
   if (m_cap > 0) uf_hook<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n, d_kept, d_err);
   uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
 }

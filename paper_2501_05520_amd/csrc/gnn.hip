@@ -47,18 +47,36 @@ __device__ __forceinline__ void load4<PrecBF16>(const __bf16* p, float& a, float
   a = (float)v[0]; b = (float)v[1]; c = (float)v[2]; d = (float)v[3];
 }
 
-// copy rows [row0, row0 + MT) of a [rows][H] act array into LDS (zero past `rows`)
+// copy rows [row0, row0 + MT) of a [rows][H] act array into LDS (zero past `rows`):
+// every load of the tile is requested before the first LDS write
 template <class P, int H, int MT, int NT>
 __device__ __forceinline__ void stage_rows(const typename P::act_t* __restrict__ g, int64_t row0, int64_t rows,
                                            typename P::act_t* lds, int ld) {
   constexpr int V = 16 / (int)sizeof(typename P::act_t);  // elements per 16-byte chunk
   constexpr int CPR = H / V;                               // chunks per row
-  for (int idx = threadIdx.x; idx < MT * CPR; idx += NT) {
+  constexpr int IT = (MT * CPR + NT - 1) / NT;
+  uint4 v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
     const int m = idx / CPR, c = idx - m * CPR;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (row0 + m < rows) v = *(const uint4*)(g + (size_t)(row0 + m) * H + c * V);
-    *(uint4*)(lds + m * ld + c * V) = v;
+    v[it] = make_uint4(0, 0, 0, 0);
+    if (idx < MT * CPR && row0 + m < rows) v[it] = *(const uint4*)(g + (size_t)(row0 + m) * H + c * V);
   }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    const int m = idx / CPR, c = idx - m * CPR;
+    if (idx < MT * CPR) *(uint4*)(lds + m * ld + c * V) = v[it];
+  }
+}
+
+// product of an LDS activation tile with a layer of compile-time fan-in K
+// (about eight weight fragments per lane in flight)
+template <class P, int MTW, int NTW, int K>
+__device__ __forceinline__ void gemm_k(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
+                                       const DevLayer& L, int nt0) {
+  tile_gemm_k<P, MTW, NTW, (K + P::KB - 1) / P::KB, (NTW >= 8 ? 1 : 8 / NTW)>(acc, xs, ldx, L.w, L.nkb, nt0);
 }
 
 // ---------------------------------------------------------------------------
@@ -77,18 +95,30 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
   const int ntiles = (n + MT - 1) / MT;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int row0 = t * MT;
-    for (int idx = threadIdx.x; idx < MT * P::KB; idx += blockDim.x) {
-      const int m = idx / P::KB, k = idx - m * P::KB;
-      xin[m * S::LDI + k] = P::cvt((k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f);
+    {
+      constexpr int IT = (MT * P::KB + NW * 64 - 1) / (NW * 64);
+      float v[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int m = idx / P::KB, k = idx - m * P::KB;
+        v[it] = (idx < MT * P::KB && k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f;
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int m = idx / P::KB, k = idx - m * P::KB;
+        if (idx < MT * P::KB) xin[m * S::LDI + k] = P::cvt(v[it]);
+      }
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
+    gemm_k<P, S::MTW, S::NTW, 3>(acc, xin, S::LDI, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, a1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+    gemm_k<P, S::MTW, S::NTW, H>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
@@ -105,7 +135,7 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
     __syncthreads();
     f32x4 accp[S::MTW][S::NTW2];
     acc_zero(accp);
-    tile_gemm<P, S::MTW, S::NTW2>(accp, a2, S::LDH, lp.w, lp.nkb, wave * S::NTW2, 0, lp.nkb);
+    gemm_k<P, S::MTW, S::NTW2, H>(accp, a2, S::LDH, lp, wave * S::NTW2);
 #pragma unroll
     for (int j = 0; j < S::NTW2; ++j) {
       const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;
@@ -138,24 +168,40 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
   const int64_t ntiles = (m + MT - 1) / MT;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
-    for (int idx = threadIdx.x; idx < MT * P::KB; idx += blockDim.x) {
-      const int mm = idx / P::KB, k = idx - mm * P::KB;
-      float v = 0.f;
-      if (k < 6 && row0 + mm < m) {
-        const int node = k < 3 ? src[row0 + mm] : dst[row0 + mm];
-        if ((unsigned)node < (unsigned)n) v = x[(size_t)node * 3 + (k % 3)];
-        else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+    {
+      constexpr int IT = (MT * P::KB + NW * 64 - 1) / (NW * 64);
+      int node[IT];
+      float v[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int mm = idx / P::KB, k = idx - mm * P::KB;
+        node[it] = -1;
+        if (idx < MT * P::KB && k < 6 && row0 + mm < m) node[it] = k < 3 ? src[row0 + mm] : dst[row0 + mm];
       }
-      xin[mm * S::LDI + k] = P::cvt(v);
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int k = idx % P::KB;
+        v[it] = 0.f;
+        if ((unsigned)node[it] < (unsigned)n) v[it] = x[(size_t)node[it] * 3 + (k % 3)];
+        else if (node[it] != -1 && d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int mm = idx / P::KB, k = idx - mm * P::KB;
+        if (idx < MT * P::KB) xin[mm * S::LDI + k] = P::cvt(v[it]);
+      }
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, xin, S::LDI, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
+    gemm_k<P, S::MTW, S::NTW, 6>(acc, xin, S::LDI, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, a1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+    gemm_k<P, S::MTW, S::NTW, H>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
@@ -199,33 +245,58 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
   const int64_t ntiles = (m + MT - 1) / MT;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
-    stage_rows<P, H, MT, NW * 64>(e, row0, m, et, S::LDH);
-    for (int mm = threadIdx.x; mm < MT; mm += blockDim.x) {
+    {
+      // the tile's edge ends are requested together with its state rows
       int a = 0, b = 0;
-      if (row0 + mm < m) {
+      const int mm = threadIdx.x;
+      if (mm < MT && row0 + mm < m) {
         a = src[row0 + mm];
         b = dst[row0 + mm];
-        if ((unsigned)a >= (unsigned)n) a = 0;
-        if ((unsigned)b >= (unsigned)n) b = 0;
       }
-      sidx[mm] = a;
-      didx[mm] = b;
+      stage_rows<P, H, MT, NW * 64>(e, row0, m, et, S::LDH);
+      if (mm < MT) {
+        sidx[mm] = (unsigned)a < (unsigned)n ? a : 0;
+        didx[mm] = (unsigned)b < (unsigned)n ? b : 0;
+      }
     }
     __syncthreads();
-    // pre[m][c] = proj[src_m][c] + proj[dst_m][H + c] + b1[c]
-    for (int idx = threadIdx.x; idx < MT * (H / V); idx += blockDim.x) {
-      const int mm = idx / (H / V), c = (idx - mm * (H / V)) * V;
-      const uint4 ua = *(const uint4*)(proj + (size_t)sidx[mm] * 2 * H + c);
-      const uint4 ub = *(const uint4*)(proj + (size_t)didx[mm] * 2 * H + H + c);
-      const T* pa = (const T*)&ua;
-      const T* pb = (const T*)&ub;
+    {
+      // pre[m][c] = proj[src_m][c] + proj[dst_m][H + c] + b1[c]: every gather of the
+      // tile is requested before the first sum is written
+      constexpr int CPR = H / V;
+      constexpr int IT = (MT * CPR + NW * 64 - 1) / (NW * 64);
+      uint4 ua[IT], ub[IT];
 #pragma unroll
-      for (int q = 0; q < V; ++q) pre[mm * LDP + c + q] = (float)pa[q] + (float)pb[q] + lc.b[c + q];
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int mm = idx / CPR, c = (idx - mm * CPR) * V;
+        ua[it] = ub[it] = make_uint4(0, 0, 0, 0);
+        if (idx < MT * CPR) {
+          ua[it] = *(const uint4*)(proj + (size_t)sidx[mm] * 2 * H + c);
+          ub[it] = *(const uint4*)(proj + (size_t)didx[mm] * 2 * H + H + c);
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NW * 64;
+        const int mm = idx / CPR, c = (idx - mm * CPR) * V;
+        if (idx < MT * CPR) {
+          const T* pa = (const T*)&ua[it];
+          const T* pb = (const T*)&ub[it];
+#pragma unroll
+          for (int q = 0; q < V; q += 4) {
+            const float4 bb = *(const float4*)(lc.b + c + q);
+            *(float4*)(pre + mm * LDP + c + q) =
+                make_float4((float)pa[q] + (float)pb[q] + bb.x, (float)pa[q + 1] + (float)pb[q + 1] + bb.y,
+                            (float)pa[q + 2] + (float)pb[q + 2] + bb.z, (float)pa[q + 3] + (float)pb[q + 3] + bb.w);
+          }
+        }
+      }
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, et, S::LDH, lc.w, lc.nkb, wave * S::NTW, 0, lc.nkb);
+    gemm_k<P, S::MTW, S::NTW, H>(acc, et, S::LDH, lc, wave * S::NTW);
     float part[S::MTW];
 #pragma unroll
     for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
@@ -271,7 +342,7 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
       }
       __syncthreads();
       acc_zero(acc);
-      tile_gemm<P, S::MTW, S::NTW>(acc, t1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+      gemm_k<P, S::MTW, S::NTW, H>(acc, t1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
       for (int j = 0; j < S::NTW; ++j) {
         const int nn = (wave * S::NTW + j) * 16 + 4 * g;
@@ -294,10 +365,12 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
 
 // ---------------------------------------------------------------------------
 // aggregation: msg[i] = sum of the states of i's incident edges, the CSR (by
-// source) list then the CSC (by destination) list, each in ascending edge order.
-// A wave serves one node; its lanes form RPS groups that each read one edge row
-// per step (16 bytes per lane), and the groups' partial sums are combined in a
-// fixed order, so the result does not depend on scheduling.
+// source) list then the CSC (by destination) list, each in ascending edge order,
+// taken as one list.  A wave serves one node at a time: one coalesced load brings
+// up to 64 edge ids of the list, then its lanes form RPS groups that each read one
+// edge row per step (16 bytes per lane); the groups' partial sums are combined in
+// a fixed order, so the result does not depend on scheduling.  The list bounds of
+// the wave's next node are requested while the current one is summed.
 // ---------------------------------------------------------------------------
 template <class P, int H>
 __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t* __restrict__ e,
@@ -312,30 +385,37 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
   const int l = lane_id();
   const int grp = l / LPR, col = (l % LPR) * V;
   const int waves = gridDim.x * (blockDim.x >> 6);
-  for (int node = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); node < n; node += waves) {
+  int node = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  int bs = 0, es = 0, bd = 0, ed = 0;
+  if (node < n) {
+    bs = sptr[node]; es = sptr[node + 1];
+    bd = dptr[node]; ed = dptr[node + 1];
+  }
+  for (; node < n; node += waves) {
+    const int nxt = node + waves;
+    int nbs = 0, nes = 0, nbd = 0, ned = 0;
+    if (nxt < n) {
+      nbs = sptr[nxt]; nes = sptr[nxt + 1];
+      nbd = dptr[nxt]; ned = dptr[nxt + 1];
+    }
     float acc[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) acc[q] = 0.f;
-    for (int pass = 0; pass < 2; ++pass) {
-      const int* ptr = pass == 0 ? sptr : dptr;
-      const int* idx = pass == 0 ? sidx : didx;
-      const int b = ptr[node], end = ptr[node + 1];
-      for (int base = b; base < end; base += 64) {
-        // the next (up to) 64 edge ids in one coalesced load; rows are then fetched
-        // with independent loads, one row per lane group and step
-        const int cnt = min(64, end - base);
-        const int my = l < cnt ? idx[base + l] : 0;
-        const int steps = (cnt + RPS - 1) / RPS;   // uniform over the wave: the shuffle needs every lane
+    const int cs = es - bs, tot = cs + (ed - bd);
+    for (int base = 0; base < tot; base += 64) {
+      const int cnt = min(64, tot - base);
+      const int k0 = base + l;
+      const int my = l < cnt ? (k0 < cs ? sidx[bs + k0] : didx[bd + k0 - cs]) : 0;
+      const int steps = (cnt + RPS - 1) / RPS;   // uniform over the wave: the shuffle needs every lane
 #pragma unroll 4
-        for (int st = 0; st < steps; ++st) {
-          const int k = grp + st * RPS;
-          const int eid = __shfl(my, k < cnt ? k : 0, 64);
-          if (k < cnt) {
-            const uint4 u = *(const uint4*)(e + (size_t)eid * H + col);
-            const T* v = (const T*)&u;
+      for (int st = 0; st < steps; ++st) {
+        const int k = grp + st * RPS;
+        const int eid = __shfl(my, k < cnt ? k : 0, 64);
+        if (k < cnt) {
+          const uint4 u = *(const uint4*)(e + (size_t)eid * H + col);
+          const T* v = (const T*)&u;
 #pragma unroll
-            for (int q = 0; q < V; ++q) acc[q] += (float)v[q];
-          }
+          for (int q = 0; q < V; ++q) acc[q] += (float)v[q];
         }
       }
     }
@@ -349,6 +429,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
       for (int q = 0; q < V; q += 4)
         *(float4*)(msg + (size_t)node * H + col + q) = make_float4(acc[q], acc[q + 1], acc[q + 2], acc[q + 3]);
     }
+    bs = nbs; es = nes; bd = nbd; ed = ned;
   }
 }
 
@@ -368,21 +449,47 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
   const int ntiles = (n + MT - 1) / MT;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int row0 = t * MT;
-    // staging of [h, m] as the working precision
-    for (int idx = threadIdx.x; idx < MT * H; idx += blockDim.x) {
-      const int mm = idx / H, col = idx - mm * H;
+    // staging of [h, m] as the working precision, and this lane's residual h values
+    // (the layout of its outputs): every load of the tile is requested first
+    constexpr int CPR = H / 4;                                  // float4 chunks per row
+    constexpr int IT = (MT * CPR + NW * 64 - 1) / (NW * 64);
+    float4 hv4[IT], mv4[IT], hres[S::MTW][S::NTW];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NW * 64;
+      const int mm = idx / CPR, c = (idx - mm * CPR) * 4;
       const int node = row0 + mm;
-      in[mm * S::LD2 + col] = P::cvt(node < n ? h[(size_t)node * H + col] : 0.f);
-      in[mm * S::LD2 + H + col] = P::cvt(node < n ? msg[(size_t)node * H + col] : 0.f);
+      hv4[it] = mv4[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < MT * CPR && node < n) {
+        hv4[it] = *(const float4*)(h + (size_t)node * H + c);
+        mv4[it] = *(const float4*)(msg + (size_t)node * H + c);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < S::MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < S::NTW; ++j) {
+        const int node = row0 + i * 16 + r;
+        const int nn = (wave * S::NTW + j) * 16 + 4 * g;
+        hres[i][j] = node < n ? *(const float4*)(h + (size_t)node * H + nn) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NW * 64;
+      const int mm = idx / CPR, c = (idx - mm * CPR) * 4;
+      if (idx < MT * CPR) {
+        P::store4(in + mm * S::LD2 + c, hv4[it].x, hv4[it].y, hv4[it].z, hv4[it].w);
+        P::store4(in + mm * S::LD2 + H + c, mv4[it].x, mv4[it].y, mv4[it].z, mv4[it].w);
+      }
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, in, S::LD2, l1.w, l1.nkb, wave * S::NTW, 0, l1.nkb);
+    gemm_k<P, S::MTW, S::NTW, 2 * H>(acc, in, S::LD2, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.b, 1.f, t1, S::LDH, wave * S::NTW);
     __syncthreads();
     acc_zero(acc);
-    tile_gemm<P, S::MTW, S::NTW>(acc, t1, S::LDH, l2.w, l2.nkb, wave * S::NTW, 0, l2.nkb);
+    gemm_k<P, S::MTW, S::NTW, H>(acc, t1, S::LDH, l2, wave * S::NTW);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
@@ -392,8 +499,7 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
       for (int i = 0; i < S::MTW; ++i) {
         const int mm = i * 16 + r;
         const int node = row0 + mm;
-        float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (node < n) hv = *(const float4*)(h + (size_t)node * H + nn);
+        float4 hv = hres[i][j];
         hv.x += trk_tanh(acc[i][j][0] + b.x);
         hv.y += trk_tanh(acc[i][j][1] + b.y);
         hv.z += trk_tanh(acc[i][j][2] + b.z);
@@ -405,7 +511,7 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
     __syncthreads();
     f32x4 accp[S::MTW][S::NTW2];
     acc_zero(accp);
-    tile_gemm<P, S::MTW, S::NTW2>(accp, in, S::LD2, lp.w, lp.nkb, wave * S::NTW2, 0, lp.nkb);
+    gemm_k<P, S::MTW, S::NTW2, H>(accp, in, S::LD2, lp, wave * S::NTW2);
 #pragma unroll
     for (int j = 0; j < S::NTW2; ++j) {
       const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;
@@ -440,6 +546,25 @@ __global__ void incidence_fill(const int* __restrict__ key, int64_t m_cap, const
   }
 }
 
+// Grid of the aggregation: by default about one node per wave (waves that finish
+// early are replaced at once, which balances uneven degrees); TRK_GNN_AGG=1 gives
+// a persistent grid of one full-occupancy set of waves walking the nodes.
+int agg_blocks(int n, int n_cu) {
+  const char* v = getenv("TRK_GNN_AGG");
+  return blocks_for(n, 4, (v && atoi(v) == 1) ? n_cu * 8 : 16384);
+}
+
+// the unrolled products read ceil(K / KB) fragment blocks per n-tile of each layer
+template <class P, int H>
+bool gnn_shapes_ok(const DevGNN& net) {
+  auto nkb = [](int K) { return (K + P::KB - 1) / P::KB; };
+  const DevLayer* sq[] = {&net.node_enc2, &net.edge_enc2, &net.edge_c, &net.edge_ab, &net.edge_2, &net.node_2,
+                          &net.out_c, &net.out_ab};
+  for (const DevLayer* L : sq)
+    if (L->nkb != nkb(H)) return false;
+  return net.H == H && net.node_enc1.nkb == nkb(3) && net.edge_enc1.nkb == nkb(6) && net.node_1.nkb == nkb(2 * H);
+}
+
 template <class P, int H, int MTE, int MTN, int NW>
 void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap, const int* d_m,
              float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
@@ -461,7 +586,7 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
       edge_kernel<P, H, MTE, NW, false><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
                                                                   net.edge_2, net.out_2, nullptr);
     const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
-    aggregate_kernel<P, H><<<blocks_for(n, 4, 16384), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
+    aggregate_kernel<P, H><<<agg_blocks(n, n_cu), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
     if (ngrid > 0)
       node_step_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
   }
@@ -509,6 +634,10 @@ void launch_incidence(const int* src, const int* dst, int64_t m_cap, const int* 
 int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
   if (n <= 0) return 0;
+  const bool f32 = prec == TRK_PREC_F32;
+  const bool ok = net.H == 128 ? (f32 ? gnn_shapes_ok<PrecF32, 128>(net) : gnn_shapes_ok<PrecBF16, 128>(net))
+                               : (f32 ? gnn_shapes_ok<PrecF32, 32>(net) : gnn_shapes_ok<PrecBF16, 32>(net));
+  if (!ok) return -1;
   if (prec == TRK_PREC_F32) {
     if (net.H == 128) { run_gnn128<PrecF32>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
     if (net.H == 32) { run_gnn<PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }

@@ -136,6 +136,39 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
   }
 }
 
+// The same product for a compile-time number of k blocks NKB (the small square
+// layers of the interaction network), fully unrolled: the weight fragments of the
+// next DIST k blocks are in flight while the current one is multiplied, and the
+// compiler can wait for each fragment individually.  nkb is the layer's stored
+// block count per n-tile (the stride of the fragment array); NKB <= nkb.
+template <class P, int MTW, int NTW, int NKB, int DIST>
+__device__ __forceinline__ void tile_gemm_k(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
+                                            const uint4* __restrict__ wb, int nkb, int nt0) {
+  typedef typename P::frag_t F;
+  constexpr int D = DIST < NKB ? DIST : NKB;
+  const int l = lane_id();
+  const int g = l >> 4, r = l & 15;
+  const typename P::act_t* xl = xs + r * ldx + g * (P::KB / 4);
+  const F* wl = (const F*)wb + (size_t)nt0 * nkb * 64 + l;
+  F w[D][NTW];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) w[d][j] = wl[((size_t)j * nkb + d) * 64];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) {
+    F xf[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) xf[i] = load_frag<P>(xl + i * 16 * ldx + kb * P::KB);
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) P::mma(acc[i][j], w[kb % D][j], xf[i]);
+      if (kb + D < NKB) w[kb % D][j] = wl[((size_t)j * nkb + kb + D) * 64];
+    }
+  }
+}
+
 // Epilogue: out = tanh(acc * dq + bias) written to an LDS tile (leading dimension
 // ldo) in the storage format of P.
 template <class P, int MTW, int NTW>

@@ -199,7 +199,9 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
 
 // Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
 // the faster shape on MI355X), 1 = two 4-wave workgroups per CU with half the rows
-// (FP8: the other row-tile height of the 8-wave workgroup).
+// (FP8: the other row-tile height of the 8-wave workgroup), 2 = FP32 only: two
+// 8-wave workgroups per CU with half the rows, so that one workgroup's epilogue
+// and barriers overlap the other's products.
 int tile_variant() {
   const char* e = getenv("TRK_MLP_TILE");
   return e ? atoi(e) : 0;
@@ -211,6 +213,7 @@ int launch_embed(int prec, int W, const float* x, int n, const DevLayer& l_in, c
                  const DevLayer& l_out, int D, float* emb, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
     if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecF32, PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024 && tile_variant() == 2) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 8>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
     if (W == 1024) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
     if (W == 64) { launch_embed_t<PrecF32, PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {
@@ -229,6 +232,7 @@ int launch_filter(int prec, int W, const float* emb, int D, const int* src, cons
                   float* scores, int n_nodes, int* d_err, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
     if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 2) { launch_filter_t<PrecF32, PrecF32, 512, 32, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 512) { launch_filter_t<PrecF32, PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 64) { launch_filter_t<PrecF32, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {

@@ -106,16 +106,22 @@ def edge_truth(pid, src, dst):
     return ((pid[src] == pid[dst]) & (pid[src] != 0)).astype(np.float32)
 
 
-def train_step(tctx, x, emb, cand, filt, y_cand, y_filt, lr=1e-3):
-    """One step: forward of both networks, summed loss, hand-written backward,
-    Adam update; returns (loss_filter, loss_gnn)."""
+def train_step(tctx, x, emb, cand, filt, y_cand, y_filt, lr=1e-3, filter=True, gnn=True):
+    """One step: forward of the selected networks, summed loss, hand-written
+    backward, Adam update; returns (loss_filter, loss_gnn)."""
     params = tctx.params.detach().requires_grad_(True)
-    zf = FilterLogits.apply(params, emb, cand[0], cand[1], tctx)
-    lf = BCEWithLogits.apply(zf, y_cand, tctx)
-    zg = GnnLogits.apply(params, x, filt[0], filt[1], tctx)
-    lg = BCEWithLogits.apply(zg, y_filt, tctx)
-    (lf + lg).backward()
-    tctx.adam_step(params.grad, lr)
+    total, lf, lg = None, torch.zeros(()), torch.zeros(())
+    if filter and cand[0].numel():
+        zf = FilterLogits.apply(params, emb, cand[0], cand[1], tctx)
+        lf = BCEWithLogits.apply(zf, y_cand, tctx)
+        total = lf
+    if gnn and filt[0].numel():
+        zg = GnnLogits.apply(params, x, filt[0], filt[1], tctx)
+        lg = BCEWithLogits.apply(zg, y_filt, tctx)
+        total = lg if total is None else total + lg
+    if total is not None:
+        total.backward()
+        tctx.adam_step(params.grad, lr)
     return float(lf), float(lg)
 
 
@@ -182,8 +188,8 @@ def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0, neg_weig
     return loss, true_frac, int(ne)
 
 
-def pipeline_step(tc, ev, lr):
-    """One filter + interaction-network step on the edge sets the current
+def pipeline_step(tc, ev, lr, filter=True, gnn=True):
+    """One filter and/or interaction-network step on the edge sets the current
     parameters produce for event ev (embedding frozen)."""
     dev = tc.device
     x = torch.as_tensor(ev.x, device=dev)
@@ -202,5 +208,25 @@ def pipeline_step(tc, ev, lr):
     ks, kd = ks[:nk], kd[:nk]
     yc = torch.as_tensor(edge_truth(ev.pid, cs.cpu().numpy(), cd.cpu().numpy()), device=dev)
     yf = torch.as_tensor(edge_truth(ev.pid, ks.cpu().numpy(), kd.cpu().numpy()), device=dev)
-    lf, lg = train_step(tc, x, emb, (cs, cd), (ks, kd), yc, yf, lr)
+    lf, lg = train_step(tc, x, emb, (cs, cd), (ks, kd), yc, yf, lr, filter=filter, gnn=gnn)
     return lf, lg, float(yc.mean()) if ne else 0.0, float(yf.mean()) if nk else 0.0
+
+
+def filter_scores_on(tc, ev):
+    """Filter scores of the candidate edges of event ev under the current
+    parameters, with their truth (host arrays)."""
+    dev = tc.device
+    x = torch.as_tensor(ev.x, device=dev)
+    emb = torch.empty((ev.n, tc.cfg.emb_dim), device=dev)
+    trk.trk_embed(tc.ctx, x, emb)
+    cap = int(tc.config.max_cand_edges)
+    cs = torch.empty(cap, dtype=torch.int32, device=dev)
+    cd = torch.empty_like(cs)
+    ne, _ = trk.trk_build_graph(tc.ctx, emb, cs, cd)
+    cs, cd = cs[:ne], cd[:ne]
+    scores = torch.empty(ne, device=dev)
+    kcap = int(tc.config.max_kept_edges)
+    ks = torch.empty(max(kcap, 1), dtype=torch.int32, device=dev)
+    kd = torch.empty_like(ks)
+    trk.trk_filter(tc.ctx, emb, cs, cd, scores, ks[:kcap], kd[:kcap])
+    return scores.cpu().numpy(), edge_truth(ev.pid, cs.cpu().numpy(), cd.cpu().numpy())
