@@ -22,7 +22,46 @@ sys.path.insert(0, ROOT)
 
 FILTER_FLOP_PER_EDGE = 2 * (2 * 512 * 512 + 512)     # hidden 512x512 layers + output dot
 EMBED_FLOP_PER_HIT = 2 * (3 * 1024 + 2 * 1024 * 1024 + 1024 * 12)
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp8all": 5000.0}
+# interaction network, H = 128, T = 8, first edge layers factorised per node
+GNN_H, GNN_T = 128, 8
+GNN_FLOP_EDGE_ITER = 2 * 2 * GNN_H * GNN_H                                  # e W_c, then W_2
+GNN_FLOP_NODE_ITER = 2 * (2 * GNN_H * GNN_H + GNN_H * GNN_H + GNN_H * 2 * GNN_H)  # node net + next projections
+GNN_FLOP_EDGE_ONCE = 2 * (6 * GNN_H + GNN_H * GNN_H) + 2 * (GNN_H * GNN_H + GNN_H)  # edge encoder, output head
+GNN_FLOP_NODE_ONCE = 2 * (3 * GNN_H + GNN_H * GNN_H + GNN_H * 2 * GNN_H)            # node encoder + projections
+HBM_PEAK_GBS = 8000.0
+ACT_BYTES = {"fp32": 4, "bf16": 2, "fp8": 2, "fp8all": 2, "bf16emb32": 2}
+
+
+def gnn_work(n_nodes, n_edges, prec):
+    """Algorithmic FLOPs and minimal HBM bytes of the interaction network per event:
+    per iteration each edge state is read and written once, node states (FP32) are
+    read, messages read and written once, projections written and read once."""
+    b = ACT_BYTES[prec]
+    flops = n_edges * (GNN_T * GNN_FLOP_EDGE_ITER + GNN_FLOP_EDGE_ONCE) + \
+        n_nodes * (GNN_T * GNN_FLOP_NODE_ITER + GNN_FLOP_NODE_ONCE)
+    per_iter = 2 * n_edges * GNN_H * b + n_nodes * GNN_H * 4 * 4 + 2 * n_nodes * 2 * GNN_H * b
+    once = n_edges * (GNN_H * b * 2 + 8 * 2 + 4) + n_nodes * (12 + GNN_H * 4)
+    return flops, GNN_T * per_iter + once
+
+
+def stage_rooflines(st, counts, prec, peak):
+    n, ec, ef, ek = counts["n_hits"], counts["n_cand_edges"], counts["n_filt_edges"], counts["n_kept_edges"]
+    gf, gb = gnn_work(n, ef, prec)
+    # components: read the kept-edge ends and scores once, write the labels a few times
+    cc_bytes = ef * 12 + n * 4 * 4
+    # radius graph: embeddings read and sorted once, edges written twice (rows, sorted)
+    graph_bytes = n * (12 * 4 * 3 + 32) + ec * 8 * 2
+    return {
+        "embed": {"bound": "mfma", "frac": round(n * EMBED_FLOP_PER_HIT / (st["embed"] * 1e-3) / 1e12 / peak, 4)},
+        "filter": {"bound": "mfma", "frac": round(ec * FILTER_FLOP_PER_EDGE / (st["filter"] * 1e-3) / 1e12 / peak, 4)},
+        "gnn": {"bound": "mfma" if prec == "fp32" else "hbm",
+                "mfma_frac": round(gf / (st["gnn"] * 1e-3) / 1e12 / peak, 4),
+                "hbm_frac": round(gb / (st["gnn"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "tflop": round(gf / 1e12, 4), "min_gbytes": round(gb / 1e9, 3)},
+        "graph": {"bound": "latency", "hbm_frac": round(graph_bytes / (st["graph"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "components": {"bound": "latency", "hbm_frac": round(cc_bytes / (st["components"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp8all": 5000.0, "bf16emb32": 2500.0}
 EVENT_SEEDS = list(range(200, 210))
 
 
@@ -31,7 +70,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "fp8all"])
+    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "fp8all", "bf16emb32"])
     p.add_argument("--no-variant", action="store_true", help="skip the BF16 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
@@ -264,7 +303,7 @@ def main():
         "metric": "events/s and p50/p99 latency per mu=200 event; per-stage MFMA/HBM roofline %",
         "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3", "fp8all": "fp8-e4m3"}[args.precision],
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3", "fp8all": "fp8-e4m3", "bf16emb32": "bf16"}[args.precision],
         "data": "synthetic helical-track events (seeded), random-init weights (seed 0)",
         "config": {"workload": "mu200 event: 110000 hits, emb 3-1024x3-12, r=0.2 K=256, filter 24-512x3-1, "
                                "IN H=128 T=8, trk_event per event", "events": len(xs),
@@ -279,15 +318,12 @@ def main():
         "roofline": {"kernel": "filter_kernel", "bound": "mfma", "achieved": round(filt_tflops, 2),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(filt_tflops / peak, 4), "traffic": None,
                      "flop_per_edge": FILTER_FLOP_PER_EDGE},
-        "stage_roofline": {
-            "embed": {"bound": "mfma", "frac": round(
-                int(np.mean([i["n_hits"] for i in infos])) * EMBED_FLOP_PER_HIT / (st["embed"] * 1e-3) / 1e12 / peak, 4)},
-            "filter": {"bound": "mfma", "frac": round(filt_tflops / peak, 4)},
-        },
+        "stage_roofline": None,
     }
+    result["stage_roofline"] = stage_rooflines(st, result["counts"], args.precision, peak)
     if not args.no_variant:
         result["variants"] = {}
-        for other in [p for p in ("fp32", "bf16", "fp8", "fp8all") if p != args.precision]:
+        for other in [p for p in ("fp32", "bf16", "bf16emb32", "fp8", "fp8all") if p != args.precision]:
             w2, lat2, inf2, lab2 = run_precision(other, cfg, nets, xs, args.steps, args.warmup, torch, trk)
             agr = [agreement(a, b) for a, b in zip(labels, lab2)]
             st2 = stage_means(inf2)
@@ -299,6 +335,10 @@ def main():
                                "p99": round(float(np.percentile(lat2, 99)) * 1e3, 3)},
                 "stage_ms": {k: round(v, 4) for k, v in st2.items()},
                 "filter_tflops": round(ft2, 2), "filter_frac_of_peak": round(ft2 / PEAK_TFLOPS[other], 4),
+                "stage_roofline": stage_rooflines(st2, {
+                    "n_hits": int(np.mean([i["n_hits"] for i in inf2])), "n_cand_edges": int(nc2),
+                    "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
+                    "n_kept_edges": int(np.mean([i["n_kept_edges"] for i in inf2]))}, other, PEAK_TFLOPS[other]),
                 "hit_agreement_vs_primary": round(float(np.mean([a[0] for a in agr])), 5),
                 "candidate_jaccard_vs_primary": round(float(np.mean([a[1] for a in agr])), 5),
                 "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),

@@ -63,6 +63,9 @@ typedef enum {
                   * and the interaction network run as in TRK_BF16.  Needs emb_hidden and
                   * filt_hidden divisible by 128. */
   TRK_FP8_ALL = 3, /* TRK_FP8 plus the embedding MLP's hidden and output layers in FP8 */
+  TRK_BF16_EMB32 = 4, /* filter and interaction network as in TRK_BF16, the embedding in FP32: the
+                       * candidate graph is the FP32 one (the radius test is the step most
+                       * sensitive to the embedding's precision) */
 } trk_precision;
 
 /* Model and sizing configuration, the analogue of a served model's config

@@ -266,19 +266,25 @@ __device__ __forceinline__ void for_neighbours(const QueryCtx& qc, WaveSlots& ws
         const int mid = (lo + hi) >> 1;
         if (ws.pre[mid] <= fidx) lo = mid; else hi = mid;
       }
+      // entry lies inside a bucket, so the cell key, the id and the embedding of the
+      // candidate are all requested at once and tested afterwards
       const int entry = ws.bstart[lo] + (fidx - ws.pre[lo]);
-      if (qc.sorted_cell[entry] == ws.key[lo]) {
-        j = qc.sorted_id[entry];
+      const unsigned long long ck = qc.sorted_cell[entry];
+      const int jj = qc.sorted_id[entry];
+      const float4* pe = (const float4*)(qc.sorted_emb + (size_t)entry * EP);
+      float4 v[EP / 4];
+#pragma unroll
+      for (int k4 = 0; k4 < EP / 4; ++k4) v[k4] = pe[k4];
+      if (ck == ws.key[lo]) {
+        j = jj;
         if (j != i) {
-          const float4* pe = (const float4*)(qc.sorted_emb + (size_t)entry * EP);
 #pragma unroll
           for (int k4 = 0; k4 < EP / 4; ++k4) {
-            const float4 v = pe[k4];
             float t;
-            t = qe[4 * k4 + 0] - v.x; d2 = fmaf(t, t, d2);
-            t = qe[4 * k4 + 1] - v.y; d2 = fmaf(t, t, d2);
-            t = qe[4 * k4 + 2] - v.z; d2 = fmaf(t, t, d2);
-            t = qe[4 * k4 + 3] - v.w; d2 = fmaf(t, t, d2);
+            t = qe[4 * k4 + 0] - v[k4].x; d2 = fmaf(t, t, d2);
+            t = qe[4 * k4 + 1] - v[k4].y; d2 = fmaf(t, t, d2);
+            t = qe[4 * k4 + 2] - v[k4].z; d2 = fmaf(t, t, d2);
+            t = qe[4 * k4 + 3] - v[k4].w; d2 = fmaf(t, t, d2);
           }
           ok = d2 < qc.r2;
         }

@@ -90,8 +90,9 @@ int validate_config(const trk_config* c) {
   if (!width_ok(c->filt_hidden, {64, 512}) || c->filt_layers < 1 || c->filt_layers > 7) return TRK_E_INVAL;
   if (!width_ok(c->gnn_hidden, {32, 128}) || c->gnn_iters < 0 || c->gnn_iters > 64) return TRK_E_INVAL;
   if (!(c->radius > 0.f) || c->k_max < 1 || c->k_max > 1024) return TRK_E_INVAL;
-  if (c->precision < TRK_FP32 || c->precision > TRK_FP8_ALL) return TRK_E_INVAL;
-  if (c->precision >= TRK_FP8 && (c->emb_hidden % 128 || c->filt_hidden % 128)) return TRK_E_INVAL;
+  if (c->precision < TRK_FP32 || c->precision > TRK_BF16_EMB32) return TRK_E_INVAL;
+  if ((c->precision == TRK_FP8 || c->precision == TRK_FP8_ALL) && (c->emb_hidden % 128 || c->filt_hidden % 128))
+    return TRK_E_INVAL;
   if (c->max_hits < 1 || c->max_hits > (1LL << 30)) return TRK_E_INVAL;
   if (c->max_cand_edges < 1 || c->max_cand_edges > (1LL << 31) - 1) return TRK_E_INVAL;
   if (c->max_kept_edges < 1 || c->max_kept_edges > (1LL << 31) - 1) return TRK_E_INVAL;
@@ -410,6 +411,7 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
     case TRK_BF16: c->prec = c->prec_emb = TRK_PREC_BF16; break;
     case TRK_FP8: c->prec = TRK_PREC_FP8; c->prec_emb = TRK_PREC_BF16; break;
     case TRK_FP8_ALL: c->prec = c->prec_emb = TRK_PREC_FP8; break;
+    case TRK_BF16_EMB32: c->prec = TRK_PREC_BF16; c->prec_emb = TRK_PREC_F32; break;
     default: c->prec = c->prec_emb = TRK_PREC_F32;
   }
   hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_id);

@@ -253,3 +253,24 @@ def test_fp8_matches_quantised_emulation(nets, mid):
     pf2 = pb.filter(e32, r["src"][sel], r["dst"][sel])[0].cpu().numpy()
     pb.close()
     assert np.array_equal(pf, pf2)
+
+
+def test_bf16_with_fp32_embedding_keeps_the_fp32_graph(pipe, nets, mid):
+    """TRK_BF16_EMB32 runs the FP32 embedding kernel, so its candidate graph is the
+    FP32 pipeline's, bit for bit; only filter and interaction-network scores move."""
+    from paper_2501_05520_amd.trk import Pipeline
+    ev, r = mid
+    pm = Pipeline(MU200, nets, "bf16emb32", max_hits=8192)
+    e_m = pm.embed(ev.x)
+    e_f = pipe.embed(ev.x)
+    assert torch.equal(e_m, e_f)
+    s_m, d_m, _ = pm.build_graph(e_m)
+    s_f, d_f, _ = pipe.build_graph(e_f)
+    assert torch.equal(s_m, s_f) and torch.equal(d_m, d_f)
+    lm, im = pm.event(ev.x)
+    pm.close()
+    lf, info = pipe.event(ev.x)
+    assert im["n_cand_edges"] == info["n_cand_edges"]
+    hit, jac = label_agreement(lm.cpu().numpy(), lf.cpu().numpy())
+    print(f"bf16emb32 vs fp32: filtered edges {im['n_filt_edges']} vs {info['n_filt_edges']}, "
+          f"hit agreement {hit:.4f} jaccard {jac:.4f}")

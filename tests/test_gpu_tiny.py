@@ -216,3 +216,29 @@ def test_capacity_reported(pipe, ref):
     with pytest.raises(trk.TrkError) as e:
         pipe.filter(r["emb"].astype(np.float32), r["src"], r["dst"], cap=10)
     assert e.value.status == -3
+
+
+def test_exact_ties_saturated(pipe):
+    """80 copies of one embedding point plus 60 spread points: every copy has 79
+    neighbours at distance exactly 0 (more than k_max = 64), so the K-cap is decided
+    by the id order alone; both sides see d^2 = 0, so the edge sets must be equal."""
+    rng = np.random.default_rng(11)
+    emb = np.concatenate([np.tile(np.full((1, TINY.emb_dim), 0.25, np.float32), (80, 1)),
+                          rng.uniform(-3, 3, (60, TINY.emb_dim)).astype(np.float32)])
+    emb = emb[rng.permutation(emb.shape[0])]
+    src, dst, nsat = pipe.build_graph(emb)
+    os_, od, cnt = oracle.radius_graph(emb, np.float32(TINY.radius), TINY.k_max)
+    assert np.array_equal(src.cpu().numpy(), os_) and np.array_equal(dst.cpu().numpy(), od)
+    assert nsat == int((cnt > TINY.k_max).sum()) >= 80
+
+
+def test_chain_with_no_filtered_edge(nets, ref):
+    """A filter cut no score can pass: the interaction network gets no edge and every
+    spacepoint is its own component."""
+    from paper_2501_05520_amd.trk import Pipeline
+    ev, _ = ref[2]
+    p = Pipeline(TINY.with_(filter_cut=1.0), nets, "fp32", max_hits=8192)
+    labels, info = p.event(ev.x)
+    p.close()
+    assert info["n_cand_edges"] > 0 and info["n_filt_edges"] == 0 and info["n_kept_edges"] == 0
+    assert np.array_equal(labels.cpu().numpy(), np.arange(ev.n))
