@@ -530,6 +530,23 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
 // incidence lists: for every node, the ids of the edges whose key (src or dst)
 // is that node, ascending
 // ---------------------------------------------------------------------------
+// row pointers of edges sorted by key: ptr[i] = first edge whose key is >= i
+__global__ void sorted_rowptr(const int* __restrict__ key, int64_t m_cap, const int* d_m, int n, int* ptr) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  GRID_STRIDE(i, (int64_t)n + 1) {
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (key[mid] < (int)i) lo = mid + 1; else hi = mid;
+    }
+    ptr[i] = (int)lo;
+  }
+}
+__global__ void iota_kernel(int* __restrict__ out, int64_t m_cap, const int* d_m) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  GRID_STRIDE(e, m) out[e] = (int)e;
+}
+
 __global__ void incidence_count(const int* __restrict__ key, int64_t m_cap, const int* d_m, int n, int* cnt) {
   const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
   GRID_STRIDE(e, m) {
@@ -567,11 +584,11 @@ bool gnn_shapes_ok(const DevGNN& net) {
 
 template <class P, int H, int MTE, int MTN, int NW>
 void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap, const int* d_m,
-             float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
+             float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool src_sorted) {
   typedef typename P::act_t T;
   T* proj = (T*)g.proj;
   T* e = (T*)g.e;
-  launch_incidence(src, dst, m_cap, d_m, n, g, s);
+  launch_incidence(src, dst, m_cap, d_m, n, g, s, src_sorted);
   const int ngrid = (int)std::min<int64_t>((n + MTN - 1) / MTN, (int64_t)n_cu * 8);
   const int64_t etiles = (m_cap + MTE - 1) / MTE;
   const int egrid = (int)std::min<int64_t>(etiles, (int64_t)n_cu * 8);
@@ -604,24 +621,31 @@ int gnn_tile_variant() {
 
 template <class P>
 void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
-                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
+                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool sorted) {
   switch (gnn_tile_variant()) {
-    case 0: run_gnn<P, 128, 64, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
-    case 2: run_gnn<P, 128, 32, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
-    case 3: run_gnn<P, 128, 32, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
-    default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); break;
+    case 0: run_gnn<P, 128, 64, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    case 2: run_gnn<P, 128, 32, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    case 3: run_gnn<P, 128, 32, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
   }
 }
 
 }  // namespace
 
 void launch_incidence(const int* src, const int* dst, int64_t m_cap, const int* d_m, int n, GnnScratch& g,
-                      hipStream_t s) {
+                      hipStream_t s, bool src_sorted) {
   const int* keys[2] = {src, dst};
   int* ptrs[2] = {g.rowptr, g.cscptr};
   int* idxs[2] = {g.rowidx, g.cscidx};
   const int eb = blocks_for(m_cap, 256, 2048);
   for (int k = 0; k < 2; ++k) {
+    if (k == 0 && src_sorted) {
+      // edges already grouped by source in ascending edge order: the list of node i
+      // is the edge range [lower_bound(src, i), lower_bound(src, i + 1))
+      sorted_rowptr<<<blocks_for((int64_t)n + 1, 256), 256, 0, s>>>(src, m_cap, d_m, n, g.rowptr);
+      iota_kernel<<<eb, 256, 0, s>>>(g.rowidx, m_cap, d_m);
+      continue;
+    }
     launch_fill_int(g.cnt, 0, n, s);
     if (m_cap > 0) incidence_count<<<eb, 256, 0, s>>>(keys[k], m_cap, d_m, n, g.cnt);
     launch_scan_excl(g.cnt, ptrs[k], n, nullptr, nullptr, g.tmp, s);
@@ -632,18 +656,18 @@ void launch_incidence(const int* src, const int* dst, int64_t m_cap, const int* 
 }
 
 int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
-               const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s) {
+               const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool src_sorted) {
   if (n <= 0) return 0;
   const bool f32 = prec == TRK_PREC_F32;
   const bool ok = net.H == 128 ? (f32 ? gnn_shapes_ok<PrecF32, 128>(net) : gnn_shapes_ok<PrecBF16, 128>(net))
                                : (f32 ? gnn_shapes_ok<PrecF32, 32>(net) : gnn_shapes_ok<PrecBF16, 32>(net));
   if (!ok) return -1;
   if (prec == TRK_PREC_F32) {
-    if (net.H == 128) { run_gnn128<PrecF32>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
-    if (net.H == 32) { run_gnn<PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 128) { run_gnn128<PrecF32>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+    if (net.H == 32) { run_gnn<PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
   } else {
-    if (net.H == 128) { run_gnn128<PrecBF16>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
-    if (net.H == 32) { run_gnn<PrecBF16, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s); return 0; }
+    if (net.H == 128) { run_gnn128<PrecBF16>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+    if (net.H == 32) { run_gnn<PrecBF16, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
   }
   return -1;
 }

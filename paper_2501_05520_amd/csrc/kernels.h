@@ -90,10 +90,13 @@ struct GnnScratch {
   int* tmp = nullptr;        // scan scratch
 };
 // CSR (by src) and CSC (by dst) incidence lists of the edges into g, edge ids ascending per node
+// src_sorted: the edges are ordered by source (ascending), so the source lists are
+// edge ranges and need no construction
 void launch_incidence(const int* src, const int* dst, int64_t m_cap, const int* d_m, int n, GnnScratch& g,
-                      hipStream_t s);
+                      hipStream_t s, bool src_sorted = false);
 int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
-               const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s);
+               const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s,
+               bool src_sorted = false);
 
 // segmented rank sort of unique int keys: for each segment [ptr[i], ptr[i+1]) of in, writes the
 // keys ascending to out at the same positions.  n segments (from d_n if given).

@@ -370,8 +370,9 @@ int run_chain(trk_ctx* c, const float* x, int n, const int* ev, int* labels, hip
   launch_compact_edges(c->cand_scores, k.filter_cut, c->cand_src, c->cand_dst, k.max_cand_edges, n_cand, c->filt_src,
                        c->filt_dst, k.max_kept_edges, n_filt, c->graph.tmp, s);
   mark(4);
+  // the filtered edges keep the radius graph's (source, destination) order
   if (launch_gnn(c->prec, c->gnn, x, n, c->filt_src, c->filt_dst, k.max_kept_edges, n_filt, c->gnn_scores, c->gs,
-                 c->n_cu, err, s))
+                 c->n_cu, err, s, true))
     return TRK_E_INVAL;
   mark(5);
   launch_components(n, c->filt_src, c->filt_dst, c->gnn_scores, k.score_cut, k.max_kept_edges, n_filt, labels,

@@ -11,7 +11,8 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libtrk.so")
+# TRK_LIB names another build of the library (e.g. one compiled with other flags)
+LIB_PATH = os.environ.get("TRK_LIB") or os.path.join(_PKG, "libtrk.so")
 
 TRK_ABI_VERSION = 1
 TRK_WEIGHTS_MAGIC = 0x5754524B
