@@ -224,6 +224,63 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
             "slots": n_slots, "clients": n_clients, "mix_mu": mus}
 
 
+def service_load(cfg, nets, precision, seconds, rate, trk, n_conn=8, seed=11, pool=6, mu=200):
+    """The socket front end on 127.0.0.1: n_conn client connections (one thread
+    each, requests in order per connection) with Poisson arrivals at `rate`
+    events/s in total; client latency (send to last label received) beside the
+    server's own (submission to completion): their difference is what the
+    transfer adds."""
+    import random
+    import threading
+    from gen import generate_event
+    xs = [generate_event(9100 + k, mu).x for k in range(pool)]
+    srv = trk.Server(cfg, nets, precision, n_slots=1, max_batch_events=8, max_batch_hits=330000,
+                     mem_budget_bytes=64 << 30)
+    svc, port = trk.trk_service_start(srv.h, "127.0.0.1", 0)
+    warm = trk.ServiceClient("127.0.0.1", port)
+    for x in xs[:2]:
+        warm.request(x)
+    warm.close()
+    client_ms, server_ms, status = [], [], []
+    lock = threading.Lock()
+    stop_at = time.perf_counter() + seconds
+
+    def conn(c):
+        rng = random.Random(seed * 100 + c)
+        cl = trk.ServiceClient("127.0.0.1", port)
+        nxt = time.perf_counter()
+        while True:
+            nxt += rng.expovariate(rate / n_conn)
+            if nxt > stop_at:
+                break
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            t0 = time.perf_counter()
+            st, _, _, lat = cl.request(xs[rng.randrange(pool)])
+            with lock:
+                client_ms.append((time.perf_counter() - t0) * 1e3)
+                server_ms.append(lat)
+                status.append(st)
+        cl.close()
+
+    th = [threading.Thread(target=conn, args=(c,)) for c in range(n_conn)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    trk.trk_service_stop(svc)
+    srv.close()
+    cm, sm = np.array(client_ms), np.array(server_ms)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 2)
+    return {"precision": precision, "connections": n_conn, "offered_events_per_s": round(rate, 2), "mu": mu,
+            "requests": int(cm.size), "errors": int(sum(1 for s in status if s != 0)),
+            "client_latency_ms": {"p50": pct(cm, 50), "p99": pct(cm, 99)},
+            "server_latency_ms": {"p50": pct(sm, 50), "p99": pct(sm, 99)},
+            "transfer_ms": {"p50": pct(cm - sm, 50), "p99": pct(cm - sm, 99)},
+            "payload_bytes": {"request": int(24 + 12 * xs[0].shape[0]), "response": int(96 + 4 * xs[0].shape[0])}}
+
+
 def train_measure(cfg, nets, steps, torch, trk):
     """Training configuration: filter + interaction network on a fresh pile-up-200
     event per step (seeds 10000+step), BCE on generator truth, hand-written
@@ -394,6 +451,12 @@ def main():
             except trk.TrkError as e:
                 sv = {"precision": prec, "slots": slots, "error": str(e)}
             result["serving_mu200"].append(sv)
+    if args.serve_seconds > 0:
+        try:
+            # the socket front end: what the transfer adds to each request
+            result["service_mu200"] = service_load(cfg, nets, "bf16", args.serve_seconds, 0.5 * value, trk)
+        except (trk.TrkError, OSError) as e:
+            result["service_mu200"] = {"error": str(e)}
     if args.train_steps > 0:
         try:
             result["training"] = train_measure(cfg, nets, args.train_steps, torch, trk)

@@ -230,8 +230,30 @@ int trk_server_wait(trk_server* srv, int64_t ticket, int32_t* h_labels, trk_even
 int trk_server_stats(trk_server* srv, trk_server_info* out);
 
 /* Drains (runs every admitted request), stops the workers and frees the slots;
- * tickets not yet waited for are released. */
+ * tickets not yet waited for are released.  Stop every service of the server first. */
 void trk_server_destroy(trk_server* srv);
+
+/* ------------------------------------------------------------------------
+ * Out-of-process front end of a server (the network side of an inference
+ * server, Section 2.3; Section 4 measures what the transfer adds): a TCP listener
+ * on host:port (IPv4 dotted address, NULL = 127.0.0.1; port 0 = any free port,
+ * written to *bound_port).  Each connection is served by its own thread, its
+ * requests in order; requests of different connections meet in the server's
+ * scheduler.  Wire format, little-endian:
+ *   request : u32 0x5154524B, u32 0, i64 n, f64 deadline_ms, f32 x[n][3]
+ *   response: u32 0x5254524B, i32 status, i64 n, f64 latency_ms (submission to
+ *             completion), i64 counts[5] (n_hits, n_cand_edges, n_filt_edges,
+ *             n_kept_edges, n_saturated), f32 stage_ms[8], then i32 labels[n] if
+ *             status == 0
+ * A bad magic, n < 0 or n > max_batch_hits gets status TRK_E_INVAL and the
+ * connection is closed.  Returns TRK_E_INVAL when the address cannot be bound.
+ * ---------------------------------------------------------------------- */
+typedef struct trk_service trk_service;
+int trk_service_start(trk_server* srv, const char* host, int port, trk_service** out, int* bound_port);
+
+/* Stops listening, ends the connections (requests in progress complete) and frees
+ * the service. */
+void trk_service_stop(trk_service* svc);
 
 /* ------------------------------------------------------------------------
  * Training of the filter MLP and the interaction network (FP32 contexts created

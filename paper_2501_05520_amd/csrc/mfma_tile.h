@@ -29,15 +29,13 @@ struct PrecF32 {
   typedef uint4 frag_t;
   static constexpr int KB = 16;          // k per fragment block
   static constexpr int PAD = 4;          // row padding in elements (16 bytes)
-  static constexpr int STEPS = 4;        // issues per fragment
-  static __device__ __forceinline__ void step(f32x4& acc, const uint4& w, const uint4& x, int s) {
-    const unsigned wv = s == 0 ? w.x : s == 1 ? w.y : s == 2 ? w.z : w.w;
-    const unsigned xv = s == 0 ? x.x : s == 1 ? x.y : s == 2 ? x.z : x.w;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(wv), __uint_as_float(xv), acc, 0, 0, 0);
-  }
+  // four dependent issues into one accumulator (interleaving them over the
+  // tile's accumulators measured slower on MI355X)
   static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) step(acc, w, x, s);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.x), __uint_as_float(x.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.y), __uint_as_float(x.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.z), __uint_as_float(x.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.w), __uint_as_float(x.w), acc, 0, 0, 0);
   }
   // store four consecutive columns
   static __device__ __forceinline__ void store4(float* p, float a, float b, float c, float d) {
@@ -52,8 +50,6 @@ struct PrecBF16 {
   typedef uint4 frag_t;
   static constexpr int KB = 32;
   static constexpr int PAD = 8;
-  static constexpr int STEPS = 1;
-  static __device__ __forceinline__ void step(f32x4& acc, const uint4& w, const uint4& x, int) { mma(acc, w, x); }
   static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
     bf16x8 a = __builtin_bit_cast(bf16x8, w);
     bf16x8 b = __builtin_bit_cast(bf16x8, x);
@@ -76,8 +72,6 @@ struct PrecFP8 {
   static constexpr int KB = 128;
   static constexpr int PAD = 16;
   static constexpr float ACT_SCALE = 256.f;
-  static constexpr int STEPS = 1;
-  static __device__ __forceinline__ void step(f32x4& acc, const i32x8& w, const i32x8& x, int) { mma(acc, w, x); }
   static __device__ __forceinline__ void mma(f32x4& acc, const i32x8& w, const i32x8& x) {
     // format 0 (E4M3) for both operands, block scales 2^(127-127) = 1
     acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, 127);
@@ -133,20 +127,6 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
     F xf[MTW];
 #pragma unroll
     for (int i = 0; i < MTW; ++i) xf[i] = load_frag<P>(xl + i * 16 * ldx + kb * P::KB);
-#ifdef TRK_MFMA_INTERLEAVE
-    // the issues of one fragment go to MTW x NTW different accumulators in turn
-#pragma unroll
-    for (int st = 0; st < P::STEPS; ++st)
-#pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-#pragma unroll
-        for (int i = 0; i < MTW; ++i) P::step(acc[i][j], w[j], xf[i], st);
-        if (st == P::STEPS - 1) {
-          w[j] = wl[((size_t)j * nkb + kbn) * 64];
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-#else
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
 #pragma unroll
@@ -155,7 +135,6 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
       // keep the issue order: n-tile j's products, then its next fragment request
       __builtin_amdgcn_sched_barrier(0);
     }
-#endif
   }
 }
 
@@ -183,23 +162,12 @@ __device__ __forceinline__ void tile_gemm_k(f32x4 (&acc)[MTW][NTW], const typena
     F xf[MTW];
 #pragma unroll
     for (int i = 0; i < MTW; ++i) xf[i] = load_frag<P>(xl + i * 16 * ldx + kb * P::KB);
-#ifdef TRK_MFMA_INTERLEAVE
-#pragma unroll
-    for (int st = 0; st < P::STEPS; ++st)
-#pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-#pragma unroll
-        for (int i = 0; i < MTW; ++i) P::step(acc[i][j], w[kb % D][j], xf[i], st);
-        if (st == P::STEPS - 1 && kb + D < NKB) w[kb % D][j] = wl[((size_t)j * nkb + kb + D) * 64];
-      }
-#else
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
 #pragma unroll
       for (int i = 0; i < MTW; ++i) P::mma(acc[i][j], w[kb % D][j], xf[i]);
       if (kb + D < NKB) w[kb % D][j] = wl[((size_t)j * nkb + kb + D) * 64];
     }
-#endif
   }
 }
 

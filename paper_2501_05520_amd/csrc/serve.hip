@@ -9,6 +9,7 @@
 
 #include "../../include/trk.h"
 #include "serve_core.h"
+#include "service_core.h"
 
 namespace {
 
@@ -70,6 +71,27 @@ struct trk_server {
   GpuExec exec;
   trk_serve::Server<GpuExec>* core = nullptr;
   uint64_t slot_bytes = 0;
+  int64_t max_hits = 0;
+};
+
+namespace {
+
+// the socket front end's view of a server
+struct ServerBackend {
+  trk_server* s;
+  int submit(const float* x, int64_t n, double deadline_ms, int64_t* ticket) {
+    return s->core->submit(x, n, deadline_ms, ticket);
+  }
+  int wait(int64_t ticket, int32_t* labels, int64_t* counts5, float* stage8, double* latency_ms) {
+    return s->core->wait(ticket, labels, counts5, stage8, latency_ms);
+  }
+};
+
+}  // namespace
+
+struct trk_service {
+  ServerBackend backend;
+  trk_net::Service<ServerBackend>* svc = nullptr;
 };
 
 namespace {
@@ -133,6 +155,7 @@ int trk_server_create(const trk_config* cfg, const void* h_weights, size_t nbyte
                                                : (uint64_t)(s->slot_bytes / (uint64_t)scfg->max_batch_hits) + 64;
   s->core = new trk_serve::Server<GpuExec>(&s->exec, scfg->n_slots, scfg->max_batch_events, scfg->max_batch_hits,
                                             scfg->mem_budget_bytes, per_hit, 4096);
+  s->max_hits = scfg->max_batch_hits;
   *out = s;
   return TRK_OK;
 }
@@ -173,6 +196,28 @@ int trk_server_stats(trk_server* s, trk_server_info* out) {
   out->peak_inflight_bytes = st.peak_inflight_bytes;
   out->slot_bytes = s->slot_bytes;
   return TRK_OK;
+}
+
+int trk_service_start(trk_server* srv, const char* host, int port, trk_service** out, int* bound_port) {
+  if (!srv || !out || port < 0 || port > 65535) return TRK_E_INVAL;
+  *out = nullptr;
+  trk_service* t = new trk_service();
+  t->backend.s = srv;
+  t->svc = new trk_net::Service<ServerBackend>(&t->backend, srv->max_hits);
+  if (t->svc->start(host, port, bound_port) != 0) {
+    delete t->svc;
+    delete t;
+    return TRK_E_INVAL;
+  }
+  *out = t;
+  return TRK_OK;
+}
+
+void trk_service_stop(trk_service* t) {
+  if (!t) return;
+  t->svc->stop();
+  delete t->svc;
+  delete t;
 }
 
 void trk_server_destroy(trk_server* s) {

@@ -24,7 +24,8 @@ EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_fil
            "trk_server_create", "trk_server_submit", "trk_server_wait", "trk_server_stats",
            "trk_server_destroy", "trk_train_param_count", "trk_train_set_params", "trk_filter_train_fwd",
            "trk_filter_train_bwd", "trk_gnn_train_fwd", "trk_gnn_train_bwd", "trk_bce_with_logits",
-           "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss")
+           "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss",
+           "trk_service_start", "trk_service_stop")
 
 
 class TrkError(RuntimeError):
@@ -115,10 +116,14 @@ def lib():
         L.trk_embed_train_fwd.argtypes = [P, P, I64, P, P]
         L.trk_embed_train_bwd.argtypes = [P, P, I64, P, P, P]
         L.trk_pair_loss.argtypes = [P, P, I64, P, P, P, I64, F, F, P, ctypes.POINTER(F), P]
+        L.trk_service_start.argtypes = [P, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P),
+                                        ctypes.POINTER(ctypes.c_int)]
+        L.trk_service_stop.argtypes = [P]
+        L.trk_service_stop.restype = None
         L.trk_strerror.argtypes = [ctypes.c_int]
         L.trk_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("trk_destroy", "trk_strerror", "trk_server_destroy"):
+            if name not in ("trk_destroy", "trk_strerror", "trk_server_destroy", "trk_service_stop"):
                 getattr(L, name).restype = ctypes.c_int
         L.trk_train_param_count.restype = ctypes.c_int64
         _lib = L
@@ -373,6 +378,63 @@ def trk_server_stats(srv):
 
 def trk_server_destroy(srv):
     lib().trk_server_destroy(srv)
+
+
+def trk_service_start(srv, host="127.0.0.1", port=0):
+    """Starts the TCP front end of a server; returns (handle, bound port)."""
+    h = ctypes.c_void_p()
+    bound = ctypes.c_int()
+    _check(lib().trk_service_start(srv, host.encode() if host else None, int(port), ctypes.byref(h),
+                                   ctypes.byref(bound)), "trk_service_start")
+    return h, bound.value
+
+
+def trk_service_stop(svc):
+    lib().trk_service_stop(svc)
+
+
+SERVICE_REQ_MAGIC, SERVICE_RESP_MAGIC = 0x5154524B, 0x5254524B
+
+
+class ServiceClient:
+    """A blocking client of the TCP front end (wire format in include/trk.h); one
+    connection, requests in order.  Pure host code: usable without a GPU."""
+
+    _REQ = struct.Struct("<IIqd")
+    _RESP = struct.Struct("<Iiqd5q8f")
+
+    def __init__(self, host, port, timeout=60.0):
+        import socket
+        self.sock = socket.create_connection((host, int(port)), timeout=timeout)
+        self.sock.setsockopt(socket.IPPROTO_TCP, socket.TCP_NODELAY, 1)
+
+    def _recv(self, n):
+        buf = bytearray(n)
+        view, got = memoryview(buf), 0
+        while got < n:
+            k = self.sock.recv_into(view[got:], n - got)
+            if k == 0:
+                raise ConnectionError("service closed the connection")
+            got += k
+        return bytes(buf)
+
+    def request(self, x, deadline_ms=0.0):
+        """Returns (status, labels int32 [n] or None, info dict, server latency ms)."""
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+        n = x.shape[0]
+        self.sock.sendall(self._REQ.pack(SERVICE_REQ_MAGIC, 0, n, float(deadline_ms)) + x.tobytes())
+        magic, status, rn, lat, *rest = self._RESP.unpack(self._recv(self._RESP.size))
+        if magic != SERVICE_RESP_MAGIC or rn != n:
+            raise ConnectionError("malformed response")
+        counts, stage = rest[:5], rest[5:]
+        info = dict(zip(("n_hits", "n_cand_edges", "n_filt_edges", "n_kept_edges", "n_saturated"), counts))
+        info["stage_ms"] = dict(zip(trk_event_info.STAGES, stage))
+        labels = np.frombuffer(self._recv(4 * n), dtype=np.int32) if status == 0 and n > 0 else \
+            (np.zeros(0, np.int32) if status == 0 else None)
+        return status, labels, info, lat
+
+    def close(self):
+        self.sock.close()
 
 
 class Server:

@@ -76,3 +76,37 @@ def test_admission_refuses_oversized_and_reports():
     rc, labels, info, lat = srv.wait(t, 500)
     assert rc == 0 and info["n_hits"] == 500
     srv.close()
+
+
+def test_socket_front_end_equals_alone():
+    """Requests through the TCP front end (several connections at once) return the
+    labels trk_event gives each event alone."""
+    from paper_2501_05520_amd import trk
+    from paper_2501_05520_amd.trk import Server, Pipeline, ServiceClient
+    nets = make_weights(TINY, 0)
+    xs = [generate_event(s, 1 + s % 2).x for s in range(30, 46)]
+    srv = Server(TINY, nets, "fp32", n_slots=2, max_batch_events=4, max_batch_hits=6000)
+    svc, port = trk.trk_service_start(srv.h, "127.0.0.1", 0)
+    results = [None] * len(xs)
+
+    def client(c):
+        cl = ServiceClient("127.0.0.1", port)
+        for k in range(c, len(xs), 4):
+            results[k] = cl.request(xs[k])
+        cl.close()
+
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    bad = ServiceClient("127.0.0.1", port).request(np.zeros((7000, 3), np.float32))   # beyond max_batch_hits
+    trk.trk_service_stop(svc)
+    srv.close()
+    assert bad[0] == -1
+    pipe = Pipeline(TINY, nets, "fp32", max_hits=6000)
+    for x, (status, labels, info, lat) in zip(xs, results):
+        alone, ainfo = pipe.event(x)
+        assert status == 0 and np.array_equal(labels, alone.cpu().numpy())
+        assert info["n_cand_edges"] == ainfo["n_cand_edges"] and lat > 0
+    pipe.close()
