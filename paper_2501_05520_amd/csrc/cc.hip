@@ -62,6 +62,26 @@ __global__ void uf_init_min(int* parent, const int* __restrict__ src, const int*
   }
 }
 
+// One round of root hooking: each kept edge whose ends have different parents
+// points the larger parent at the smaller one (atomicMin keeps parent[x] <= x and
+// the smaller candidate when several edges hook the same root).  After pointer
+// jumping every spacepoint points at a root again; a few such rounds link most of
+// each component using only fire-and-forget atomics, and the compare-and-swap
+// pass below completes what is left.
+__global__ void uf_hook_min(int* parent, const int* __restrict__ src, const int* __restrict__ dst,
+                            const float* __restrict__ scores, float cut, int64_t m_cap, const int* d_m, int n) {
+  const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
+  GRID_STRIDE(e, m) {
+    if (!scores || scores[e] > cut) {
+      const int a = src[e], b = dst[e];
+      if ((unsigned)a < (unsigned)n && (unsigned)b < (unsigned)n) {
+        const int pa = parent[a], pb = parent[b];
+        if (pa != pb) atomicMin(&parent[pa > pb ? pa : pb], pa > pb ? pb : pa);
+      }
+    }
+  }
+}
+
 __global__ void uf_hook(int* parent, const int* __restrict__ src, const int* __restrict__ dst,
                         const float* __restrict__ scores, float cut, int64_t m_cap, const int* d_m, int n,
                         int* d_kept, int* d_err) {
@@ -109,6 +129,10 @@ void launch_components(int n, const int* src, const int* dst, const float* score
     // the initial forest has chains of decreasing ids; pointing every spacepoint at
     // the end of its chain first keeps the finds of the union pass short
     uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
+    for (int round = 0; round < 4; ++round) {
+      uf_hook_min<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n);
+      uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
+    }
   }
   if (m_cap > 0)
     uf_hook<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n, d_kept, d_err);

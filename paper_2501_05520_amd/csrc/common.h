@@ -20,13 +20,15 @@ __device__ __forceinline__ float trk_exp(float x) {
   return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }
 
-// tanh(x) = 1 - 2 / (exp(2x) + 1) on x clamped to [-9, 9] (tanh(9) rounds to 1 in
-// float32 within 3e-8): one exponential, one reciprocal, no sign handling.
-__device__ __forceinline__ float trk_tanh(float x) {
-  x = __builtin_amdgcn_fmed3f(x, -9.0f, 9.0f);
-  const float t = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // exp(2x)
-  return fmaf(-2.0f, __builtin_amdgcn_rcpf(t + 1.0f), 1.0f);
+// tanh(x) = 1 - 2 / (exp(2x) + 1), from y = 2 x log2(e): one exponential, one
+// reciprocal.  No clamp is needed: for large y the exponential overflows to +inf,
+// whose reciprocal is 0 (tanh = 1), and for very negative y it underflows to 0
+// (tanh = -1).  Callers that compute a * s + b fold log2(e) into s and b.
+constexpr float TRK_2LOG2E = 2.8853900817779268f;
+__device__ __forceinline__ float trk_tanh_log2(float y) {
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f), 1.0f);
 }
+__device__ __forceinline__ float trk_tanh(float x) { return trk_tanh_log2(x * TRK_2LOG2E); }
 
 __device__ __forceinline__ float trk_sigmoid(float z) {
   z = __builtin_amdgcn_fmed3f(z, -80.0f, 80.0f);

@@ -22,6 +22,11 @@ namespace {
 
 constexpr int KIN = 32;  // padded width of the encoder inputs (3 or 6 features)
 
+// a bias vector times 2 log2(e), for epilogues tanh(acc + b) = trk_tanh_log2(acc * 2 log2(e) + b')
+__device__ __forceinline__ float4 scaled4(float4 b) {
+  return make_float4(b.x * TRK_2LOG2E, b.y * TRK_2LOG2E, b.z * TRK_2LOG2E, b.w * TRK_2LOG2E);
+}
+
 template <class P, int H, int MT, int NW>
 struct GnnShape {
   typedef typename P::act_t T;
@@ -73,10 +78,10 @@ __device__ __forceinline__ void stage_rows(const typename P::act_t* __restrict__
 
 // product of an LDS activation tile with a layer of compile-time fan-in K
 // (about eight weight fragments per lane in flight)
-template <class P, int MTW, int NTW, int K>
+template <class P, int MTW, int NTW, int K, bool INIT = false>
 __device__ __forceinline__ void gemm_k(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
                                        const DevLayer& L, int nt0) {
-  tile_gemm_k<P, MTW, NTW, (K + P::KB - 1) / P::KB, (NTW >= 8 ? 1 : 8 / NTW)>(acc, xs, ldx, L.w, L.nkb, nt0);
+  tile_gemm_k<P, MTW, NTW, (K + P::KB - 1) / P::KB, (NTW >= 8 ? 1 : 8 / NTW), INIT>(acc, xs, ldx, L.w, L.nkb, nt0);
 }
 
 // ---------------------------------------------------------------------------
@@ -113,29 +118,26 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, 3>(acc, xin, S::LDI, l1, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, 3, true>(acc, xin, S::LDI, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, H>(acc, a1, S::LDH, l2, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = *(const float4*)(l2.b + nn);
+      const float4 b = scaled4(*(const float4*)(l2.b + nn));
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int m = i * 16 + r;
-        const float v0 = trk_tanh(acc[i][j][0] + b.x), v1 = trk_tanh(acc[i][j][1] + b.y);
-        const float v2 = trk_tanh(acc[i][j][2] + b.z), v3 = trk_tanh(acc[i][j][3] + b.w);
+        const float v0 = trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x)), v1 = trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y));
+        const float v2 = trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z)), v3 = trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w));
         if (row0 + m < n) *(float4*)(h + (size_t)(row0 + m) * H + nn) = make_float4(v0, v1, v2, v3);
         P::store4(a2 + m * S::LDH + nn, v0, v1, v2, v3);
       }
     }
     __syncthreads();
     f32x4 accp[S::MTW][S::NTW2];
-    acc_zero(accp);
-    gemm_k<P, S::MTW, S::NTW2, H>(accp, a2, S::LDH, lp, wave * S::NTW2);
+        gemm_k<P, S::MTW, S::NTW2, H, true>(accp, a2, S::LDH, lp, wave * S::NTW2);
 #pragma unroll
     for (int j = 0; j < S::NTW2; ++j) {
       const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;
@@ -196,22 +198,20 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, 6>(acc, xin, S::LDI, l1, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, 6, true>(acc, xin, S::LDI, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, H>(acc, a1, S::LDH, l2, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = *(const float4*)(l2.b + nn);
+      const float4 b = scaled4(*(const float4*)(l2.b + nn));
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int64_t row = row0 + i * 16 + r;
         if (row < m)
-          P::store4(e + (size_t)row * H + nn, trk_tanh(acc[i][j][0] + b.x), trk_tanh(acc[i][j][1] + b.y),
-                    trk_tanh(acc[i][j][2] + b.z), trk_tanh(acc[i][j][3] + b.w));
+          P::store4(e + (size_t)row * H + nn, trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x)), trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y)),
+                    trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z)), trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w)));
       }
     }
     __syncthreads();
@@ -295,8 +295,7 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, H>(acc, et, S::LDH, lc, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, H, true>(acc, et, S::LDH, lc, wave * S::NTW);
     float part[S::MTW];
 #pragma unroll
     for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
@@ -341,12 +340,11 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
           P::store4(t1 + (i * 16 + r) * S::LDH + nn, acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
       }
       __syncthreads();
-      acc_zero(acc);
-      gemm_k<P, S::MTW, S::NTW, H>(acc, t1, S::LDH, l2, wave * S::NTW);
+            gemm_k<P, S::MTW, S::NTW, H, true>(acc, t1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
       for (int j = 0; j < S::NTW; ++j) {
         const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-        const float4 b = *(const float4*)(l2.b + nn);
+        const float4 b = scaled4(*(const float4*)(l2.b + nn));
 #pragma unroll
         for (int i = 0; i < S::MTW; ++i) {
           const int mm = i * 16 + r;
@@ -354,8 +352,8 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
           float e0, e1, e2, e3;
           load4<P>(et + mm * S::LDH + nn, e0, e1, e2, e3);
           if (row < m)
-            P::store4(e + (size_t)row * H + nn, e0 + trk_tanh(acc[i][j][0] + b.x), e1 + trk_tanh(acc[i][j][1] + b.y),
-                      e2 + trk_tanh(acc[i][j][2] + b.z), e3 + trk_tanh(acc[i][j][3] + b.w));
+            P::store4(e + (size_t)row * H + nn, e0 + trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x)), e1 + trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y)),
+                      e2 + trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z)), e3 + trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w)));
         }
       }
       __syncthreads();
@@ -484,34 +482,31 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, 2 * H>(acc, in, S::LD2, l1, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, 2 * H, true>(acc, in, S::LD2, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.b, 1.f, t1, S::LDH, wave * S::NTW);
     __syncthreads();
-    acc_zero(acc);
-    gemm_k<P, S::MTW, S::NTW, H>(acc, t1, S::LDH, l2, wave * S::NTW);
+        gemm_k<P, S::MTW, S::NTW, H, true>(acc, t1, S::LDH, l2, wave * S::NTW);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = *(const float4*)(l2.b + nn);
+      const float4 b = scaled4(*(const float4*)(l2.b + nn));
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int mm = i * 16 + r;
         const int node = row0 + mm;
         float4 hv = hres[i][j];
-        hv.x += trk_tanh(acc[i][j][0] + b.x);
-        hv.y += trk_tanh(acc[i][j][1] + b.y);
-        hv.z += trk_tanh(acc[i][j][2] + b.z);
-        hv.w += trk_tanh(acc[i][j][3] + b.w);
+        hv.x += trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x));
+        hv.y += trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y));
+        hv.z += trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z));
+        hv.w += trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w));
         if (node < n) *(float4*)(h + (size_t)node * H + nn) = hv;
         P::store4(in + mm * S::LD2 + nn, hv.x, hv.y, hv.z, hv.w);
       }
     }
     __syncthreads();
     f32x4 accp[S::MTW][S::NTW2];
-    acc_zero(accp);
-    gemm_k<P, S::MTW, S::NTW2, H>(accp, in, S::LD2, lp, wave * S::NTW2);
+        gemm_k<P, S::MTW, S::NTW2, H, true>(accp, in, S::LD2, lp, wave * S::NTW2);
 #pragma unroll
     for (int j = 0; j < S::NTW2; ++j) {
       const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;

@@ -22,6 +22,8 @@
 #pragma once
 #include "common.h"
 
+#include <type_traits>
+
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 struct PrecF32 {
@@ -31,6 +33,13 @@ struct PrecF32 {
   static constexpr int PAD = 4;          // row padding in elements (16 bytes)
   // four dependent issues into one accumulator (interleaving them over the
   // tile's accumulators measured slower on MI355X)
+  static __device__ __forceinline__ void mma_first(f32x4& acc, const uint4& w, const uint4& x) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.x), __uint_as_float(x.x), f32x4{0.f, 0.f, 0.f, 0.f},
+                                               0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.y), __uint_as_float(x.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.z), __uint_as_float(x.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.w), __uint_as_float(x.w), acc, 0, 0, 0);
+  }
   static __device__ __forceinline__ void mma(f32x4& acc, const uint4& w, const uint4& x) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.x), __uint_as_float(x.x), acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(w.y), __uint_as_float(x.y), acc, 0, 0, 0);
@@ -55,6 +64,11 @@ struct PrecBF16 {
     bf16x8 b = __builtin_bit_cast(bf16x8, x);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
   }
+  static __device__ __forceinline__ void mma_first(f32x4& acc, const uint4& w, const uint4& x) {
+    bf16x8 a = __builtin_bit_cast(bf16x8, w);
+    bf16x8 b = __builtin_bit_cast(bf16x8, x);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  }
   static __device__ __forceinline__ void store4(__bf16* p, float a, float b, float c, float d) {
     bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
     *(bf16x4*)p = v;
@@ -75,6 +89,9 @@ struct PrecFP8 {
   static __device__ __forceinline__ void mma(f32x4& acc, const i32x8& w, const i32x8& x) {
     // format 0 (E4M3) for both operands, block scales 2^(127-127) = 1
     acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, acc, 0, 0, 0, 127, 0, 127);
+  }
+  static __device__ __forceinline__ void mma_first(f32x4& acc, const i32x8& w, const i32x8& x) {
+    acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, 127, 0, 127);
   }
   static __device__ __forceinline__ void store4(uint8_t* p, float a, float b, float c, float d) {
     int v = __builtin_amdgcn_cvt_pk_fp8_f32(a * ACT_SCALE, b * ACT_SCALE, 0, false);
@@ -102,9 +119,11 @@ __device__ __forceinline__ void acc_zero(f32x4 (&acc)[MTW][NTW]) {
 }
 
 // acc[i][j] += X[rows of m-tile i] * W[:, n-tile nt0 + j] over fragment blocks
-// kb0 .. kb0 + nkb_run - 1 of a layer with nkb blocks per n-tile.
-// xs: LDS activation tile (row-major, leading dimension ldx elements), row 0 = m-tile 0.
-template <class P, int MTW, int NTW>
+// kb0 .. kb0 + nkb_run - 1 of a layer with nkb blocks per n-tile (INIT: acc = the
+// product; the first block's issues take a zero accumulator, so acc needs no
+// clearing; requires nkb_run >= 1, which every layer has).  xs: LDS activation
+// tile (row-major, leading dimension ldx elements), row 0 = m-tile 0.
+template <class P, int MTW, int NTW, bool INIT = false>
 __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
                                           const uint4* __restrict__ wb, int nkb, int nt0, int kb0,
                                           int nkb_run) {
@@ -113,13 +132,14 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
   const typename P::act_t* xl = xs + r * ldx + g * (P::KB / 4);
   typedef typename P::frag_t F;
   const F* wl = (const F*)wb + (size_t)nt0 * nkb * 64 + l;
-  if (nkb_run <= 0) return;
+  if (!INIT && nkb_run <= 0) return;
   // one weight fragment per n-tile in flight: the fragment of n-tile j for the next k
   // block is requested as soon as the current one has been consumed
   F w[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) w[j] = wl[((size_t)j * nkb + kb0) * 64];
-  for (int kk = 0; kk < nkb_run; ++kk) {
+  // one k block; FIRST: the issues start from a zero accumulator
+  auto block = [&](int kk, auto first) {
     const int kb = kb0 + kk;
     // the last block re-reads itself so that every load is unconditional and the
     // compiler can wait for each fragment individually
@@ -130,12 +150,21 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
 #pragma unroll
-      for (int i = 0; i < MTW; ++i) P::mma(acc[i][j], w[j], xf[i]);
+      for (int i = 0; i < MTW; ++i) {
+        if constexpr (decltype(first)::value) P::mma_first(acc[i][j], w[j], xf[i]);
+        else P::mma(acc[i][j], w[j], xf[i]);
+      }
       w[j] = wl[((size_t)j * nkb + kbn) * 64];
       // keep the issue order: n-tile j's products, then its next fragment request
       __builtin_amdgcn_sched_barrier(0);
     }
+  };
+  int kk = 0;
+  if constexpr (INIT) {
+    block(0, std::true_type{});
+    kk = 1;
   }
+  for (; kk < nkb_run; ++kk) block(kk, std::false_type{});
 }
 
 // The same product for a compile-time number of k blocks NKB (the small square
@@ -143,7 +172,7 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MTW][NTW], const typename
 // next DIST k blocks are in flight while the current one is multiplied, and the
 // compiler can wait for each fragment individually.  nkb is the layer's stored
 // block count per n-tile (the stride of the fragment array); NKB <= nkb.
-template <class P, int MTW, int NTW, int NKB, int DIST>
+template <class P, int MTW, int NTW, int NKB, int DIST, bool INIT = false>
 __device__ __forceinline__ void tile_gemm_k(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
                                             const uint4* __restrict__ wb, int nkb, int nt0) {
   typedef typename P::frag_t F;
@@ -165,7 +194,10 @@ __device__ __forceinline__ void tile_gemm_k(f32x4 (&acc)[MTW][NTW], const typena
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
 #pragma unroll
-      for (int i = 0; i < MTW; ++i) P::mma(acc[i][j], w[kb % D][j], xf[i]);
+      for (int i = 0; i < MTW; ++i) {
+        if (INIT && kb == 0) P::mma_first(acc[i][j], w[kb % D][j], xf[i]);
+        else P::mma(acc[i][j], w[kb % D][j], xf[i]);
+      }
       if (kb + D < NKB) w[kb % D][j] = wl[((size_t)j * nkb + kb + D) * 64];
     }
   }
@@ -178,15 +210,17 @@ __device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], co
                                                 float dq, typename P::act_t* out, int ldo, int nt0) {
   const int l = lane_id();
   const int g = l >> 4, r = l & 15;
+  const float s = dq * TRK_2LOG2E;
 #pragma unroll
   for (int j = 0; j < NTW; ++j) {
     const int n = (nt0 + j) * 16 + 4 * g;
-    const float4 b = *(const float4*)(bias + n);
+    float4 b = *(const float4*)(bias + n);
+    b = make_float4(b.x * TRK_2LOG2E, b.y * TRK_2LOG2E, b.z * TRK_2LOG2E, b.w * TRK_2LOG2E);
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
       const f32x4 a = acc[i][j];
-      P::store4(out + (i * 16 + r) * ldo + n, trk_tanh(fmaf(a[0], dq, b.x)), trk_tanh(fmaf(a[1], dq, b.y)),
-                trk_tanh(fmaf(a[2], dq, b.z)), trk_tanh(fmaf(a[3], dq, b.w)));
+      P::store4(out + (i * 16 + r) * ldo + n, trk_tanh_log2(fmaf(a[0], s, b.x)), trk_tanh_log2(fmaf(a[1], s, b.y)),
+                trk_tanh_log2(fmaf(a[2], s, b.z)), trk_tanh_log2(fmaf(a[3], s, b.w)));
     }
   }
 }

@@ -59,13 +59,11 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-    acc_zero(acc);
-    tile_gemm<P0, S::MTW, S::NTW>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
+        tile_gemm<P0, S::MTW, S::NTW, true>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
     tile_store_tanh<P>(acc, l_in.b, l_in.dq, act, S::LD, nt0);
     __syncthreads();
     for (int h = 0; h < hid.n; ++h) {
-      acc_zero(acc);
-      tile_gemm<P, S::MTW, S::NTW>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
+            tile_gemm<P, S::MTW, S::NTW, true>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
       __syncthreads();
       tile_store_tanh<P>(acc, hid.l[h].b, hid.l[h].dq, act, S::LD, nt0);
       __syncthreads();
@@ -132,11 +130,10 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
     for (int layer = 0; layer < nlayers; ++layer) {
       const DevLayer& L = layer == 0 ? l_in : hid.l[layer - 1];
       f32x4 acc[S::MTW][S::NTW];
-      acc_zero(acc);
       if (layer == 0)
-        tile_gemm<P0, S::MTW, S::NTW>(acc, xin, S::LDI, L.w, L.nkb, nt0, 0, L.nkb);
+        tile_gemm<P0, S::MTW, S::NTW, true>(acc, xin, S::LDI, L.w, L.nkb, nt0, 0, L.nkb);
       else
-        tile_gemm<P, S::MTW, S::NTW>(acc, act, S::LD, L.w, L.nkb, nt0, 0, L.nkb);
+        tile_gemm<P, S::MTW, S::NTW, true>(acc, act, S::LD, L.w, L.nkb, nt0, 0, L.nkb);
       if (layer + 1 < nlayers) {
         if (layer > 0) __syncthreads();
         tile_store_tanh<P>(acc, L.b, L.dq, act, S::LD, nt0);
@@ -144,19 +141,20 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
       } else {
         // last hidden layer: fold the single-output layer into the epilogue
         float part[S::MTW];
-        const float dq = L.dq;
+        const float sc = L.dq * TRK_2LOG2E;
 #pragma unroll
         for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
 #pragma unroll
         for (int j = 0; j < S::NTW; ++j) {
           const int n = (nt0 + j) * 16 + 4 * g;
-          const float4 b = *(const float4*)(L.b + n);
+          float4 b = *(const float4*)(L.b + n);
+          b = make_float4(b.x * TRK_2LOG2E, b.y * TRK_2LOG2E, b.z * TRK_2LOG2E, b.w * TRK_2LOG2E);
           const float4 w = *(const float4*)(out.w + n);
 #pragma unroll
           for (int i = 0; i < S::MTW; ++i) {
             const f32x4 a = acc[i][j];
-            part[i] += trk_tanh(fmaf(a[0], dq, b.x)) * w.x + trk_tanh(fmaf(a[1], dq, b.y)) * w.y +
-                       trk_tanh(fmaf(a[2], dq, b.z)) * w.z + trk_tanh(fmaf(a[3], dq, b.w)) * w.w;
+            part[i] += trk_tanh_log2(fmaf(a[0], sc, b.x)) * w.x + trk_tanh_log2(fmaf(a[1], sc, b.y)) * w.y +
+                       trk_tanh_log2(fmaf(a[2], sc, b.z)) * w.z + trk_tanh_log2(fmaf(a[3], sc, b.w)) * w.w;
           }
         }
 #pragma unroll

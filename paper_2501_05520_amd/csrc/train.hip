@@ -106,8 +106,7 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __rest
     __syncthreads();
     for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
       f32x4 acc[MTW][NTW];
-      acc_zero(acc);
-      tile_gemm<PrecF32, MTW, NTW>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
+            tile_gemm<PrecF32, MTW, NTW, true>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
         const int n0 = (nt0 + j) * 16 + 4 * g;
