@@ -11,6 +11,7 @@
 // edges were processed.
 #include "kernels.h"
 #include "common.h"
+#include <stdlib.h>
 
 namespace {
 
@@ -71,14 +72,39 @@ __global__ void uf_init_min(int* parent, const int* __restrict__ src, const int*
 __global__ void uf_hook_min(int* parent, const int* __restrict__ src, const int* __restrict__ dst,
                             const float* __restrict__ scores, float cut, int64_t m_cap, const int* d_m, int n) {
   const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
-  GRID_STRIDE(e, m) {
-    if (!scores || scores[e] > cut) {
+  const int l = lane_id();
+  // whole waves step through the edges together (the combining below needs every lane)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < m; base += stride) {
+    const int64_t e = base + l;
+    int tgt = -1, val = 0x7fffffff;
+    if (e < m && (!scores || scores[e] > cut)) {
       const int a = src[e], b = dst[e];
       if ((unsigned)a < (unsigned)n && (unsigned)b < (unsigned)n) {
         const int pa = parent[a], pb = parent[b];
-        if (pa != pb) atomicMin(&parent[pa > pb ? pa : pb], pa > pb ? pb : pa);
+        if (pa != pb) {
+          tgt = pa > pb ? pa : pb;
+          val = pa > pb ? pb : pa;
+        }
       }
     }
+    // edges are ordered by source, so neighbouring lanes often hook the same root:
+    // runs of equal targets take their minimum by a segmented scan and only the
+    // run's last lane issues the atomic
+    // segmented inclusive min-scan; a run starts at lane 0 or where the target changes
+    const int t_prev = __shfl_up(tgt, 1, 64);
+    int head = (l == 0 || t_prev != tgt) ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v_o = __shfl_up(val, o, 64), h_o = __shfl_up(head, o, 64);
+      if (l >= o) {
+        if (!head && v_o < val) val = v_o;
+        head |= h_o;
+      }
+    }
+    const int t_next = __shfl_down(tgt, 1, 64);
+    const bool last = l == 63 || t_next != tgt;
+    if (tgt >= 0 && last) atomicMin(&parent[tgt], val);
   }
 }
 
@@ -118,6 +144,12 @@ __global__ void uf_compress(int* parent, int n) {
   }
 }
 
+// atomicMin rounds before the compare-and-swap pass (TRK_UF_ROUNDS overrides)
+int uf_rounds() {
+  const char* v = getenv("TRK_UF_ROUNDS");
+  return v ? atoi(v) : 2;
+}
+
 }  // namespace
 
 void launch_components(int n, const int* src, const int* dst, const float* scores, float cut, int64_t m_cap,
@@ -129,7 +161,7 @@ void launch_components(int n, const int* src, const int* dst, const float* score
     // the initial forest has chains of decreasing ids; pointing every spacepoint at
     // the end of its chain first keeps the finds of the union pass short
     uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
-    for (int round = 0; round < 4; ++round) {
+    for (int round = 0; round < uf_rounds(); ++round) {
       uf_hook_min<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n);
       uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
     }

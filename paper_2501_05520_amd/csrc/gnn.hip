@@ -22,10 +22,6 @@ namespace {
 
 constexpr int KIN = 32;  // padded width of the encoder inputs (3 or 6 features)
 
-// a bias vector times 2 log2(e), for epilogues tanh(acc + b) = trk_tanh_log2(acc * 2 log2(e) + b')
-__device__ __forceinline__ float4 scaled4(float4 b) {
-  return make_float4(b.x * TRK_2LOG2E, b.y * TRK_2LOG2E, b.z * TRK_2LOG2E, b.w * TRK_2LOG2E);
-}
 
 template <class P, int H, int MT, int NW>
 struct GnnShape {
@@ -119,13 +115,13 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
         gemm_k<P, S::MTW, S::NTW, 3, true>(acc, xin, S::LDI, l1, wave * S::NTW);
-    tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
+    tile_store_tanh<P>(acc, l1.bs, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
         gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = scaled4(*(const float4*)(l2.b + nn));
+      const float4 b = *(const float4*)(l2.bs + nn);
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int m = i * 16 + r;
@@ -199,13 +195,13 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
         gemm_k<P, S::MTW, S::NTW, 6, true>(acc, xin, S::LDI, l1, wave * S::NTW);
-    tile_store_tanh<P>(acc, l1.b, 1.f, a1, S::LDH, wave * S::NTW);
+    tile_store_tanh<P>(acc, l1.bs, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
         gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = scaled4(*(const float4*)(l2.b + nn));
+      const float4 b = *(const float4*)(l2.bs + nn);
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int64_t row = row0 + i * 16 + r;
@@ -261,7 +257,7 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
     }
     __syncthreads();
     {
-      // pre[m][c] = proj[src_m][c] + proj[dst_m][H + c] + b1[c]: every gather of the
+      // pre[m][c] = (proj[src_m][c] + proj[dst_m][H + c] + b1[c]) 2 log2(e): every gather of the
       // tile is requested before the first sum is written
       constexpr int CPR = H / V;
       constexpr int IT = (MT * CPR + NW * 64 - 1) / (NW * 64);
@@ -285,10 +281,13 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
           const T* pb = (const T*)&ub[it];
 #pragma unroll
           for (int q = 0; q < V; q += 4) {
-            const float4 bb = *(const float4*)(lc.b + c + q);
+            // kept times 2 log2(e), the form the tanh epilogue consumes
+            const float4 bb = *(const float4*)(lc.bs + c + q);
             *(float4*)(pre + mm * LDP + c + q) =
-                make_float4((float)pa[q] + (float)pb[q] + bb.x, (float)pa[q + 1] + (float)pb[q + 1] + bb.y,
-                            (float)pa[q + 2] + (float)pb[q + 2] + bb.z, (float)pa[q + 3] + (float)pb[q + 3] + bb.w);
+                make_float4(fmaf((float)pa[q] + (float)pb[q], TRK_2LOG2E, bb.x),
+                            fmaf((float)pa[q + 1] + (float)pb[q + 1], TRK_2LOG2E, bb.y),
+                            fmaf((float)pa[q + 2] + (float)pb[q + 2], TRK_2LOG2E, bb.z),
+                            fmaf((float)pa[q + 3] + (float)pb[q + 3], TRK_2LOG2E, bb.w));
           }
         }
       }
@@ -308,10 +307,10 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
       for (int i = 0; i < S::MTW; ++i) {
         const int mm = i * 16 + r;
         const float4 pv = *(const float4*)(pre + mm * LDP + nn);
-        const float v0 = trk_tanh(acc[i][j][0] + pv.x);
-        const float v1 = trk_tanh(acc[i][j][1] + pv.y);
-        const float v2 = trk_tanh(acc[i][j][2] + pv.z);
-        const float v3 = trk_tanh(acc[i][j][3] + pv.w);
+        const float v0 = trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, pv.x));
+        const float v1 = trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, pv.y));
+        const float v2 = trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, pv.z));
+        const float v3 = trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, pv.w));
         if (OUT) part[i] += v0 * w2.x + v1 * w2.y + v2 * w2.z + v3 * w2.w;
         acc[i][j] = f32x4{v0, v1, v2, v3};
       }
@@ -344,7 +343,7 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
 #pragma unroll
       for (int j = 0; j < S::NTW; ++j) {
         const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-        const float4 b = scaled4(*(const float4*)(l2.b + nn));
+        const float4 b = *(const float4*)(l2.bs + nn);
 #pragma unroll
         for (int i = 0; i < S::MTW; ++i) {
           const int mm = i * 16 + r;
@@ -483,14 +482,14 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
         gemm_k<P, S::MTW, S::NTW, 2 * H, true>(acc, in, S::LD2, l1, wave * S::NTW);
-    tile_store_tanh<P>(acc, l1.b, 1.f, t1, S::LDH, wave * S::NTW);
+    tile_store_tanh<P>(acc, l1.bs, 1.f, t1, S::LDH, wave * S::NTW);
     __syncthreads();
         gemm_k<P, S::MTW, S::NTW, H, true>(acc, t1, S::LDH, l2, wave * S::NTW);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
-      const float4 b = scaled4(*(const float4*)(l2.b + nn));
+      const float4 b = *(const float4*)(l2.bs + nn);
 #pragma unroll
       for (int i = 0; i < S::MTW; ++i) {
         const int mm = i * 16 + r;

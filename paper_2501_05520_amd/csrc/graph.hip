@@ -90,9 +90,6 @@ __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ p
                                                     float radius, double* __restrict__ basis) {
   __shared__ double st[NSTAT];
   __shared__ double C[EP][EP];
-  __shared__ double V[3][EP];
-  __shared__ double Wm[3][EP];
-  __shared__ double dots[3];
   const int t = threadIdx.x;
   if (t < NSTAT) {
     double s = 0.0;
@@ -113,63 +110,44 @@ __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ p
     }
     C[a][b] = v;
   }
-  if (t < 3 * EP) {
-    const int c = t / EP, k = t % EP;
-    // fixed dense start, distinct per column
-    V[c][k] = (k < D) ? cos(0.7 * (k + 1) * (c + 1) + 0.3 * c) : 0.0;
-  }
   __syncthreads();
+  // the iteration runs in one wave, in registers: lane l < 3 EP holds V[l / EP][l % EP]
+  if (t >= 64) return;
+  const int l = t, c = l / EP, k = l % EP;
+  auto wave_sum = [](double d) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    return d;
+  };
+  // fixed dense start, distinct per column
+  double v = (l < 3 * EP && k < D) ? cos(0.7 * (k + 1) * (c + 1) + 0.3 * c) : 0.0;
   for (int it = 0; it < 24; ++it) {
-    if (t < 3 * EP) {
-      const int c = t / EP, k = t % EP;
-      double s = 0.0;
-      for (int q = 0; q < EP; ++q) s += C[k][q] * V[c][q];
-      // keep a small multiple of the start vector so rank-deficient covariances still
-      // leave three independent columns
-      Wm[c][k] = s + 1e-12 * V[c][k];
+    double w = 0.0;
+    for (int q = 0; q < EP; ++q) w += C[k][q] * __shfl(v, (c < 3 ? c : 3) * EP + q, 64);
+    // keep a small multiple of the start vector so rank-deficient covariances still
+    // leave three independent columns
+    w += 1e-12 * v;
+    // modified Gram-Schmidt on the three columns, in order
+    for (int cc = 0; cc < 3; ++cc) {
+      for (int p = 0; p < cc; ++p) {
+        const double wp = __shfl(w, p * EP + k, 64);
+        const double d = wave_sum(c == cc ? w * wp : 0.0);
+        if (c == cc) w -= d * wp;
+      }
+      const double nn = wave_sum(c == cc ? w * w : 0.0);
+      if (c == cc) w *= nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     }
-    __syncthreads();
-    // modified Gram-Schmidt on the three columns (serial over columns)
-    for (int c = 0; c < 3; ++c) {
-      for (int p = 0; p < c; ++p) {
-        if (t == 0) {
-          double d = 0.0;
-          for (int k = 0; k < EP; ++k) d += Wm[c][k] * Wm[p][k];
-          dots[0] = d;
-        }
-        __syncthreads();
-        if (t < EP) Wm[c][t] -= dots[0] * Wm[p][t];
-        __syncthreads();
-      }
-      if (t == 0) {
-        double d = 0.0;
-        for (int k = 0; k < EP; ++k) d += Wm[c][k] * Wm[c][k];
-        dots[1] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-      }
-      __syncthreads();
-      if (t < EP) Wm[c][t] *= dots[1];
-      __syncthreads();
+    v = w;
+  }
+  // the columns must come out orthonormal; a degenerate run falls back to coordinate axes
+  bool ok = true;
+  for (int cc = 0; cc < 3; ++cc)
+    for (int p = 0; p <= cc; ++p) {
+      const double d = wave_sum(c == cc ? v * __shfl(v, p * EP + k, 64) : 0.0);
+      ok = ok && fabs(d - (p == cc ? 1.0 : 0.0)) < 1e-9;
     }
-    if (t < 3 * EP) V[t / EP][t % EP] = Wm[t / EP][t % EP];
-    __syncthreads();
-  }
-  __shared__ int ok_s;
-  if (t == 0) {
-    // the columns must come out orthonormal; a degenerate run falls back to coordinate axes
-    bool ok = true;
-    for (int c = 0; c < 3; ++c)
-      for (int p = 0; p <= c; ++p) {
-        double d = 0.0;
-        for (int k = 0; k < EP; ++k) d += V[c][k] * V[p][k];
-        ok = ok && fabs(d - (p == c ? 1.0 : 0.0)) < 1e-9;
-      }
-    ok_s = ok ? 1 : 0;
-  }
-  __syncthreads();
-  if (t < 3 * EP) basis[t] = ok_s ? V[t / EP][t % EP] : (((t % EP) == (t / EP)) ? 1.0 : 0.0);
-  if (t == 0) {
-    basis[3 * EP] = (double)radius * (1.0 + CELL_MARGIN);
-  }
+  if (l < 3 * EP) basis[l] = ok ? v : (k == c ? 1.0 : 0.0);
+  if (l == 0) basis[3 * EP] = (double)radius * (1.0 + CELL_MARGIN);
 }
 
 // ---------------------------------------------------------------------------

@@ -9,6 +9,7 @@ struct DevLayer {
   int nkb = 0, nnt = 0;          // fragment blocks along k, 16-column tiles along n
   const uint4* w = nullptr;      // fragment blocks in the layer's storage precision
   const float* b = nullptr;      // bias, fp32, zero-padded to nnt * 16
+  const float* bs = nullptr;     // the bias times 2 log2(e), for tanh epilogues computed from 2^y
   float dq = 1.f;                // dequantisation factor of the products (1 unless FP8)
 };
 

@@ -204,9 +204,9 @@ __device__ __forceinline__ void tile_gemm_k(f32x4 (&acc)[MTW][NTW], const typena
 }
 
 // Epilogue: out = tanh(acc * dq + bias) written to an LDS tile (leading dimension
-// ldo) in the storage format of P.
+// ldo) in the storage format of P; bias_s is the bias times 2 log2(e).
 template <class P, int MTW, int NTW>
-__device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], const float* __restrict__ bias,
+__device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], const float* __restrict__ bias_s,
                                                 float dq, typename P::act_t* out, int ldo, int nt0) {
   const int l = lane_id();
   const int g = l >> 4, r = l & 15;
@@ -214,8 +214,7 @@ __device__ __forceinline__ void tile_store_tanh(const f32x4 (&acc)[MTW][NTW], co
 #pragma unroll
   for (int j = 0; j < NTW; ++j) {
     const int n = (nt0 + j) * 16 + 4 * g;
-    float4 b = *(const float4*)(bias + n);
-    b = make_float4(b.x * TRK_2LOG2E, b.y * TRK_2LOG2E, b.z * TRK_2LOG2E, b.w * TRK_2LOG2E);
+    const float4 b = *(const float4*)(bias_s + n);
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
       const f32x4 a = acc[i][j];

@@ -60,12 +60,12 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
         tile_gemm<P0, S::MTW, S::NTW, true>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
-    tile_store_tanh<P>(acc, l_in.b, l_in.dq, act, S::LD, nt0);
+    tile_store_tanh<P>(acc, l_in.bs, l_in.dq, act, S::LD, nt0);
     __syncthreads();
     for (int h = 0; h < hid.n; ++h) {
             tile_gemm<P, S::MTW, S::NTW, true>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
       __syncthreads();
-      tile_store_tanh<P>(acc, hid.l[h].b, hid.l[h].dq, act, S::LD, nt0);
+      tile_store_tanh<P>(acc, hid.l[h].bs, hid.l[h].dq, act, S::LD, nt0);
       __syncthreads();
     }
     // output layer: a single 16-column tile, its k range split over the waves
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
         tile_gemm<P, S::MTW, S::NTW, true>(acc, act, S::LD, L.w, L.nkb, nt0, 0, L.nkb);
       if (layer + 1 < nlayers) {
         if (layer > 0) __syncthreads();
-        tile_store_tanh<P>(acc, L.b, L.dq, act, S::LD, nt0);
+        tile_store_tanh<P>(acc, L.bs, L.dq, act, S::LD, nt0);
         __syncthreads();
       } else {
         // last hidden layer: fold the single-output layer into the epilogue
@@ -147,8 +147,7 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
 #pragma unroll
         for (int j = 0; j < S::NTW; ++j) {
           const int n = (nt0 + j) * 16 + 4 * g;
-          float4 b = *(const float4*)(L.b + n);
-          b = make_float4(b.x * TRK_2LOG2E, b.y * TRK_2LOG2E, b.z * TRK_2LOG2E, b.w * TRK_2LOG2E);
+          const float4 b = *(const float4*)(L.bs + n);
           const float4 w = *(const float4*)(out.w + n);
 #pragma unroll
           for (int i = 0; i < S::MTW; ++i) {

@@ -78,8 +78,14 @@ __global__ void frag_fill_kernel(uint4* out, int nkb, int nnt, int K, int N, Mat
   }
 }
 
-__global__ void bias_fill_kernel(float* out, int nout, const float* b, int N) {
-  GRID_STRIDE(i, nout) out[i] = i < N ? b[i] : 0.f;
+// bias (zero-padded to nout) and, when out_s is given, the same times 2 log2(e)
+// (the inference epilogues' pre-scaled copy)
+__global__ void bias_fill_kernel(float* out, float* out_s, int nout, const float* b, int N) {
+  GRID_STRIDE(i, nout) {
+    const float v = i < N ? b[i] : 0.f;
+    out[i] = v;
+    if (out_s) out_s[i] = v * TRK_2LOG2E;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,7 +523,8 @@ void fill(const DevLayer& L, int K, int N, MatView A, MatView B, int mode, int s
           hipStream_t s) {
   const int64_t nblk = (int64_t)L.nkb * L.nnt * 64;
   frag_fill_kernel<<<blocks_for(nblk, 256), 256, 0, s>>>((uint4*)L.w, L.nkb, L.nnt, K, N, A, B, mode, split, bf16);
-  bias_fill_kernel<<<blocks_for(L.nnt * 16, 256), 256, 0, s>>>((float*)L.b, L.nnt * 16, bias, bias ? N : 0);
+  bias_fill_kernel<<<blocks_for(L.nnt * 16, 256), 256, 0, s>>>((float*)L.b, (float*)L.bs, L.nnt * 16, bias,
+                                                               bias ? N : 0);
 }
 
 MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {

@@ -147,7 +147,7 @@ HostLinear side_by_side(const HostLinear& L, int ra, int rb, int K) {
 
 struct WeightUpload {
   std::vector<uint8_t> bytes;
-  struct Fix { DevLayer* L; size_t wofs, bofs; };
+  struct Fix { DevLayer* L; size_t wofs, bofs, bsofs; };
   struct VecFix { DevVec* V; size_t wofs; };
   std::vector<Fix> fixes;
   std::vector<VecFix> vfixes;
@@ -164,11 +164,15 @@ struct WeightUpload {
     // an FP8 layer reads FP8 activations (stored times FP8_ACT_SCALE) and FP8 weights
     D.dq = prec == TRK_PREC_FP8 ? 1.f / (scale * FP8_ACT_SCALE) : 1.f;
     std::vector<uint8_t> f = make_fragments(L.w.data(), L.K, L.N, prec, D.nkb, D.nnt, scale);
-    std::vector<float> b((size_t)D.nnt * 16, 0.f);
-    for (int n = 0; n < L.N; ++n) b[n] = L.b[n];
+    std::vector<float> b((size_t)D.nnt * 16, 0.f), bs((size_t)D.nnt * 16, 0.f);
+    for (int n = 0; n < L.N; ++n) {
+      b[n] = L.b[n];
+      bs[n] = (float)((double)L.b[n] * 2.8853900817779268);   // 2 log2(e)
+    }
     const size_t wo = put(f.data(), f.size());
     const size_t bo = put(b.data(), b.size() * 4);
-    fixes.push_back({&D, wo, bo});
+    const size_t bso = put(bs.data(), bs.size() * 4);
+    fixes.push_back({&D, wo, bo, bso});
   }
   void vec(DevVec& V, const HostLinear& L) {  // L is K x 1
     V.K = L.K;
@@ -181,6 +185,7 @@ struct WeightUpload {
     for (auto& f : fixes) {
       f.L->w = (const uint4*)((char*)base + f.wofs);
       f.L->b = (const float*)((char*)base + f.bofs);
+      f.L->bs = (const float*)((char*)base + f.bsofs);
     }
     for (auto& v : vfixes) v.V->w = (const float*)((char*)base + v.wofs);
   }
