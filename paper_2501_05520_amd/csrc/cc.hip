@@ -147,7 +147,7 @@ __global__ void uf_compress(int* parent, int n) {
 // atomicMin rounds before the compare-and-swap pass (TRK_UF_ROUNDS overrides)
 int uf_rounds() {
   const char* v = getenv("TRK_UF_ROUNDS");
-  return v ? atoi(v) : 2;
+  return v ? atoi(v) : 4;
 }
 
 }  // namespace
