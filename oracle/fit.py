@@ -17,7 +17,9 @@ reading taken here, for a solenoid field B along z:
   atan2(b, a) + q pi / 2;
 * longitudinal: s = 2 R asin(min(1, rho / 2R)) (transverse arc length from the
   origin), least-squares line z = z0 + s tan(lambda); eta = asinh(tan(lambda));
-* chi2_xy = mean over hits of (|x - c| - R)^2 in mm^2.
+* chi2_xy = mean over hits of (|x - c| - R)^2 in mm^2;
+* collinear or coincident transverse positions define no circle: all six
+  parameters are NaN.
 
 Returns, for candidates in ascending label order: label, n_hits and
 params = (pT, phi0, eta, z0 [mm], q, chi2_xy).
@@ -33,6 +35,9 @@ def positions(x):
 
 def fit_candidate(X, Y, Z, rho, b_field):
     A = np.stack([X, Y, np.ones_like(X)], axis=1)
+    if np.linalg.matrix_rank(A) < 3:
+        # collinear or coincident transverse positions: no circle is defined
+        return np.full(6, np.nan)
     (D, E, F), *_ = np.linalg.lstsq(A, -(X * X + Y * Y), rcond=None)
     a, b = -D / 2.0, -E / 2.0
     R = np.sqrt(max(a * a + b * b - F, 0.0))

@@ -55,3 +55,12 @@ def test_min_hits_and_ordering():
     l3, n3, _ = F.fit_candidates(ev.x, lab, min_hits=3)
     l11, _, _ = F.fit_candidates(ev.x, lab, min_hits=11)
     assert np.all(np.diff(l3) > 0) and len(l11) == 0 and np.all(n3 >= 3)
+
+
+def test_degenerate_candidates_are_nan():
+    # three hits on one line through the origin, and three coincident hits
+    line = np.array([[0.1, 0.25, 0.0], [0.2, 0.25, 0.1], [0.3, 0.25, 0.2]], np.float32)
+    same = np.tile(np.array([[0.5, 0.1, 0.0]], np.float32), (3, 1))
+    x = np.concatenate([line, same])
+    _, _, par = F.fit_candidates(x, [0, 0, 0, 3, 3, 3], min_hits=3)
+    assert np.all(np.isnan(par))
