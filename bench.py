@@ -281,6 +281,36 @@ def service_load(cfg, nets, precision, seconds, rate, trk, n_conn=8, seed=11, po
             "payload_bytes": {"request": int(24 + 12 * xs[0].shape[0]), "response": int(96 + 4 * xs[0].shape[0])}}
 
 
+def fit_measure(cfg, nets, ev, labels_chain, torch, trk, reps=5):
+    """Downstream helix fit (trk_fit) of one pile-up-200 event: on the chain's own
+    candidates and on the generator's particles as candidates (the latter also
+    gives the pT resolution against the generated values)."""
+    pipe = trk.Pipeline(cfg, nets, "fp32", max_hits=ev.n + 64)
+    x = torch.as_tensor(ev.x, device="cuda")
+    lab_truth = np.arange(ev.n)
+    for p in np.unique(ev.pid[ev.pid > 0]):
+        idx = np.flatnonzero(ev.pid == p)
+        lab_truth[idx] = idx.min()
+    out = {}
+    for name, lab in (("chain_candidates", labels_chain), ("generated_particles", lab_truth)):
+        l = torch.as_tensor(np.asarray(lab, np.int32), device="cuda")
+        trk.trk_fit(pipe.ctx, x, l)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            cl, cn, par = trk.trk_fit(pipe.ctx, x, l)
+        torch.cuda.synchronize()
+        out[name] = {"candidates": int(cl.numel()), "ms": round((time.perf_counter() - t0) / reps * 1e3, 3)}
+        if name == "generated_particles":
+            par = par.cpu().numpy()
+            pid = ev.pid[cl.cpu().numpy()] - 1
+            rel = par[:, 0] / ev.truth["pt"][pid] - 1.0
+            out[name]["pt_rel_error_rms"] = float(np.sqrt(np.mean(rel ** 2)))
+            out[name]["charge_correct"] = float(np.mean(par[:, 4] == ev.truth["q"][pid]))
+    pipe.close()
+    return out
+
+
 def train_measure(cfg, nets, steps, torch, trk):
     """Training configuration: filter + interaction network on a fresh pile-up-200
     event per step (seeds 10000+step), BCE on generator truth, hand-written
@@ -457,6 +487,10 @@ def main():
             result["service_mu200"] = service_load(cfg, nets, "bf16", args.serve_seconds, 0.5 * value, trk)
         except (trk.TrkError, OSError) as e:
             result["service_mu200"] = {"error": str(e)}
+    try:
+        result["downstream_fit"] = fit_measure(cfg, nets, evs[0], labels[0], torch, trk)
+    except trk.TrkError as e:
+        result["downstream_fit"] = {"error": str(e)}
     if args.train_steps > 0:
         try:
             result["training"] = train_measure(cfg, nets, args.train_steps, torch, trk)

@@ -234,6 +234,25 @@ int trk_server_stats(trk_server* srv, trk_server_info* out);
 void trk_server_destroy(trk_server* srv);
 
 /* ------------------------------------------------------------------------
+ * Downstream helix fit of track candidates (what consumes the chain's output,
+ * Section 2.2.2): every label value carried by at least min_hits spacepoints of
+ * d_x[n][3] (the chain's features, rho/1000 mm, phi/pi, z/1000 mm) is a candidate.
+ * Per candidate, in ascending label order: the algebraic least-squares circle in
+ * the transverse plane and the least-squares line z = z0 + s tan(lambda) over the
+ * transverse arc length s, for a solenoid field of b_field_t tesla along z.
+ * Outputs (device, caller-owned, capacity cap): d_cand_label[c], d_cand_nhits[c],
+ * d_params[c][6] = (pT GeV, phi0 at the point of closest approach to the origin,
+ * eta, z0 mm, charge +-1, mean squared transverse residual mm^2) in FP64.
+ * *n_cands (host) = number of candidates; more than cap: TRK_E_CAPACITY (nothing
+ * beyond cap written).  Labels must lie in [0, n) (trk_event's do), else
+ * TRK_E_INVAL.  Hits with collinear or coincident transverse positions give NaN.
+ * Synchronises the stream.
+ * ---------------------------------------------------------------------- */
+int trk_fit(trk_ctx* ctx, const float* d_x, int64_t n, const int32_t* d_labels, int32_t min_hits,
+            double b_field_t, int32_t* d_cand_label, int32_t* d_cand_nhits, double* d_params, int64_t cap,
+            int64_t* n_cands, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Out-of-process front end of a server (the network side of an inference
  * server, Section 2.3; Section 4 measures what the transfer adds): a TCP listener
  * on host:port (IPv4 dotted address, NULL = 127.0.0.1; port 0 = any free port,

@@ -277,6 +277,13 @@ int alloc_scratch(trk_ctx* c) {
   a.add(c->filt_dst, CF);
   a.add(c->gnn_scores, CF);
   a.add(c->ev, NH);
+  a.add(c->fit_cnt, NH + 1);
+  a.add(c->fit_flag, NH + 1);
+  a.add(c->fit_cidx, NH + 1);
+  a.add(c->fit_start, NH + 1);
+  a.add(c->fit_cursor, NH);
+  a.add(c->fit_raw, NH);
+  a.add(c->fit_hits, NH);
   a.add(c->offs, (size_t)k.max_events + 1);
   a.add(c->dev_words, 16);
   a.add(c->batch_counts, (size_t)k.max_events * 4);

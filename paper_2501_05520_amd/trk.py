@@ -25,7 +25,7 @@ EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_fil
            "trk_server_destroy", "trk_train_param_count", "trk_train_set_params", "trk_filter_train_fwd",
            "trk_filter_train_bwd", "trk_gnn_train_fwd", "trk_gnn_train_bwd", "trk_bce_with_logits",
            "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss",
-           "trk_service_start", "trk_service_stop")
+           "trk_service_start", "trk_service_stop", "trk_fit")
 
 
 class TrkError(RuntimeError):
@@ -116,6 +116,7 @@ def lib():
         L.trk_embed_train_fwd.argtypes = [P, P, I64, P, P]
         L.trk_embed_train_bwd.argtypes = [P, P, I64, P, P, P]
         L.trk_pair_loss.argtypes = [P, P, I64, P, P, P, I64, F, F, P, ctypes.POINTER(F), P]
+        L.trk_fit.argtypes = [P, P, I64, P, I32, ctypes.c_double, P, P, P, I64, ctypes.POINTER(I64), P]
         L.trk_service_start.argtypes = [P, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P),
                                         ctypes.POINTER(ctypes.c_int)]
         L.trk_service_stop.argtypes = [P]
@@ -378,6 +379,24 @@ def trk_server_stats(srv):
 
 def trk_server_destroy(srv):
     lib().trk_server_destroy(srv)
+
+
+def trk_fit(ctx, x, labels, min_hits=3, b_field=2.0, cap=None, stream=None):
+    """Helix fit of the candidates of labels[n] over x[n][3] (device tensors);
+    returns (labels int32 [c], n_hits int32 [c], params float64 [c][6])."""
+    n = x.shape[0]
+    cap = int(cap if cap is not None else max(n // 3, 1))
+    dev = x.device
+    cl = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    cn = torch.empty_like(cl)
+    par = torch.empty((max(cap, 1), 6), dtype=torch.float64, device=dev)
+    nc = ctypes.c_int64()
+    rc = lib().trk_fit(ctx, _ptr(x), n, _ptr(labels), int(min_hits), float(b_field), _ptr(cl), _ptr(cn), _ptr(par),
+                       cap, ctypes.byref(nc), _stream(stream))
+    if rc != 0:
+        raise TrkError(rc, f"trk_fit (needs {nc.value} candidates)")
+    k = nc.value
+    return cl[:k], cn[:k], par[:k]
 
 
 def trk_service_start(srv, host="127.0.0.1", port=0):
