@@ -66,6 +66,10 @@ typedef enum {
   TRK_BF16_EMB32 = 4, /* filter and interaction network as in TRK_BF16, the embedding in FP32: the
                        * candidate graph is the FP32 one (the radius test is the step most
                        * sensitive to the embedding's precision) */
+  TRK_BF16X3 = 5, /* every matrix product on the BF16 MFMA units in split form: each FP32 operand
+                   * is carried as hi = bf16(v) plus lo = bf16(v - hi) (within 2^-18 of v) and a
+                   * product is hi*hi + hi*lo + lo*hi with FP32 accumulation; activations are
+                   * stored as the two parts (4 bytes).  The narrow first MLP layers run in FP32. */
 } trk_precision;
 
 /* Model and sizing configuration, the analogue of a served model's config

@@ -70,7 +70,8 @@ struct trk_ctx {
   // helix fit (fit.hip): per-label counts, flags, candidate index, segment starts,
   // fill cursors, hit ids grouped by label (unsorted, sorted)
   int *fit_cnt = nullptr, *fit_flag = nullptr, *fit_cidx = nullptr, *fit_start = nullptr;
-  int *fit_cursor = nullptr, *fit_raw = nullptr, *fit_hits = nullptr;
+  int *fit_keys = nullptr, *fit_keys2 = nullptr, *fit_raw = nullptr, *fit_hits = nullptr;
+  int *fit_hist = nullptr, *fit_hoff = nullptr;   // radix digit counts per block, their offsets
   int* host_words = nullptr;  // pinned mirror
   int64_t* host_offs = nullptr;  // pinned staging of batch offsets [max_events + 1]
   int* host_counts = nullptr;    // pinned per-event counts [max_events][4]

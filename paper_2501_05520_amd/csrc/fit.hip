@@ -11,9 +11,11 @@
 //     motion at the point of closest approach to the origin;
 //   longitudinal: least-squares line z = z0 + s tan(lambda) over the arc length
 //     s = 2 R asin(rho / 2R), eta = asinh(tan(lambda)).
-// Hits are grouped by label with a counting sort whose segments are then sorted
-// by hit id, and each wave sums its candidate's moments in a fixed order, so the
-// results do not depend on scheduling.
+// Hits are grouped by label with a stable least-significant-digit radix sort of
+// the hit ids keyed by label (8-bit digits), so that each candidate's hits come in
+// ascending id order, and each wave sums its candidate's moments in a fixed order:
+// the results do not depend on scheduling, and the sort costs the same for a giant
+// candidate as for many small ones.
 #include <math.h>
 
 #include "../../include/trk.h"
@@ -35,11 +37,72 @@ __global__ void label_flags(const int* __restrict__ cnt, int n, int min_hits, in
   GRID_STRIDE(l, n) flag[l] = cnt[l] >= min_hits ? 1 : 0;
 }
 
-__global__ void label_fill(const int* __restrict__ labels, int n, const int* __restrict__ start, int* cursor,
-                           int* raw) {
-  GRID_STRIDE(i, n) {
-    const int l = labels[i];
-    if ((unsigned)l < (unsigned)n) raw[start[l] + atomicAdd(&cursor[l], 1)] = (int)i;
+// Radix pass, step 1: count of each digit (key >> shift) & 255 in every chunk of
+// FIT_SORT_CHUNK keys, stored digit-major (hist[d * nb + chunk]) so that one
+// exclusive scan gives every (digit, chunk) its first output position.
+constexpr int RS_THREADS = 256;
+constexpr int RS_ROUNDS = FIT_SORT_CHUNK / RS_THREADS;
+
+__global__ __launch_bounds__(RS_THREADS) void radix_hist(const int* __restrict__ keys, int n, int shift, int nb,
+                                                         int* __restrict__ hist) {
+  __shared__ int cnt[256];
+  const int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * FIT_SORT_CHUNK;
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t e = base + r * RS_THREADS + t;
+    if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(size_t)t * nb + blockIdx.x] = cnt[t];
+}
+
+// Radix pass, step 2: stable scatter.  The chunk is taken in rounds of 256 keys in
+// index order; an element's place among the equal digits of its round is its rank
+// in its wave's match group (eight ballots) plus the counts of the same digit in the
+// round's earlier waves, after the counts of the chunk's earlier rounds.
+// vin == nullptr: the values are the indices themselves.
+__global__ __launch_bounds__(RS_THREADS) void radix_scatter(const int* __restrict__ kin, const int* __restrict__ vin,
+                                                            int n, int shift, int nb, const int* __restrict__ off,
+                                                            int* __restrict__ kout, int* __restrict__ vout) {
+  constexpr int NWV = RS_THREADS / 64;
+  __shared__ int base[256], running[256], wc[NWV][256];
+  const int t = threadIdx.x, w = t >> 6, l = lane_id();
+  base[t] = off[(size_t)t * nb + blockIdx.x];
+  running[t] = 0;
+  const unsigned long long below = l == 0 ? 0ull : (~0ull >> (64 - l));
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+#pragma unroll
+    for (int q = 0; q < NWV; ++q) wc[q][t] = 0;
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * FIT_SORT_CHUNK + r * RS_THREADS + t;
+    const bool valid = e < n;
+    const int k = valid ? kin[e] : 0;
+    const int v = valid ? (vin ? vin[e] : (int)e) : 0;
+    const int d = (k >> shift) & 255;
+    unsigned long long m = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const unsigned long long bb = ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    // the highest lane of a match group records the group's size
+    if (valid && (m >> l) == 1ull) wc[w][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      int pos = base[d] + running[d] + __popcll(m & below);
+      for (int q = 0; q < w; ++q) pos += wc[q][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int q = 0; q < NWV; ++q) add += wc[q][t];
+    running[t] += add;
   }
 }
 
@@ -187,9 +250,26 @@ extern "C" int trk_fit(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d
   label_flags<<<blocks_for(nn, 256), 256, 0, s>>>(c->fit_cnt, nn, min_hits, c->fit_flag);
   launch_scan_excl(c->fit_flag, c->fit_cidx, nn, nullptr, d_total, c->graph.tmp, s);
   launch_scan_excl(c->fit_cnt, c->fit_start, nn, nullptr, nullptr, c->graph.tmp, s);
-  launch_fill_int(c->fit_cursor, 0, nn, s);
-  label_fill<<<blocks_for(nn, 256), 256, 0, s>>>(d_labels, nn, c->fit_start, c->fit_cursor, c->fit_raw);
-  launch_segment_sort(c->fit_start, c->fit_raw, c->fit_hits, nn, s);
+  // hit ids ordered by (label, id): passes over the digits of keys < n, the last
+  // pass writing into fit_hits
+  {
+    int bits = 1;
+    while (bits < 31 && (1 << bits) < nn) ++bits;
+    const int passes = (bits + 7) / 8;
+    const int nb = (int)fit_sort_blocks(nn);
+    int* kbuf[2] = {c->fit_keys, c->fit_keys2};
+    int* vbuf[2] = {c->fit_raw, c->fit_hits};
+    const int* kin = d_labels;
+    const int* vin = nullptr;
+    for (int p = 0; p < passes; ++p) {
+      const int o = (passes - 1 - p) % 2 == 0 ? 1 : 0;
+      radix_hist<<<nb, RS_THREADS, 0, s>>>(kin, nn, 8 * p, nb, c->fit_hist);
+      launch_scan_excl(c->fit_hist, c->fit_hoff, (int64_t)256 * nb, nullptr, nullptr, c->graph.tmp, s);
+      radix_scatter<<<nb, RS_THREADS, 0, s>>>(kin, vin, nn, 8 * p, nb, c->fit_hoff, kbuf[o], vbuf[o]);
+      kin = kbuf[o];
+      vin = vbuf[o];
+    }
+  }
   if (cap > 0) {
     cand_list<<<blocks_for(nn, 256), 256, 0, s>>>(c->fit_cnt, c->fit_cidx, nn, min_hits, cap, d_cand_label,
                                                    d_cand_nhits);

@@ -47,6 +47,12 @@ __device__ __forceinline__ void load4<PrecBF16>(const __bf16* p, float& a, float
   const bf16x4 v = *(const bf16x4*)p;
   a = (float)v[0]; b = (float)v[1]; c = (float)v[2]; d = (float)v[3];
 }
+template <>
+__device__ __forceinline__ void load4<PrecX3>(const x3_t* p, float& a, float& b, float& c, float& d) {
+  float v[4];
+  PrecX3::unpack16(*(const uint4*)p, v);
+  a = v[0]; b = v[1]; c = v[2]; d = v[3];
+}
 
 // copy rows [row0, row0 + MT) of a [rows][H] act array into LDS (zero past `rows`):
 // every load of the tile is requested before the first LDS write
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
         const int m = idx / P::KB, k = idx - m * P::KB;
-        if (idx < MT * P::KB) xin[m * S::LDI + k] = P::cvt(v[it]);
+        if (idx < MT * P::KB) P::store1(xin + m * S::LDI, k, v[it]);
       }
     }
     __syncthreads();
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
         const int mm = idx / P::KB, k = idx - mm * P::KB;
-        if (idx < MT * P::KB) xin[mm * S::LDI + k] = P::cvt(v[it]);
+        if (idx < MT * P::KB) P::store1(xin + mm * S::LDI, k, v[it]);
       }
     }
     __syncthreads();
@@ -277,17 +283,18 @@ __global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __rest
         const int idx = threadIdx.x + it * NW * 64;
         const int mm = idx / CPR, c = (idx - mm * CPR) * V;
         if (idx < MT * CPR) {
-          const T* pa = (const T*)&ua[it];
-          const T* pb = (const T*)&ub[it];
+          float pa[V], pb[V];
+          P::unpack16(ua[it], pa);
+          P::unpack16(ub[it], pb);
 #pragma unroll
           for (int q = 0; q < V; q += 4) {
             // kept times 2 log2(e), the form the tanh epilogue consumes
             const float4 bb = *(const float4*)(lc.bs + c + q);
             *(float4*)(pre + mm * LDP + c + q) =
-                make_float4(fmaf((float)pa[q] + (float)pb[q], TRK_2LOG2E, bb.x),
-                            fmaf((float)pa[q + 1] + (float)pb[q + 1], TRK_2LOG2E, bb.y),
-                            fmaf((float)pa[q + 2] + (float)pb[q + 2], TRK_2LOG2E, bb.z),
-                            fmaf((float)pa[q + 3] + (float)pb[q + 3], TRK_2LOG2E, bb.w));
+                make_float4(fmaf(pa[q] + pb[q], TRK_2LOG2E, bb.x),
+                            fmaf(pa[q + 1] + pb[q + 1], TRK_2LOG2E, bb.y),
+                            fmaf(pa[q + 2] + pb[q + 2], TRK_2LOG2E, bb.z),
+                            fmaf(pa[q + 3] + pb[q + 3], TRK_2LOG2E, bb.w));
           }
         }
       }
@@ -409,10 +416,10 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
         const int k = grp + st * RPS;
         const int eid = __shfl(my, k < cnt ? k : 0, 64);
         if (k < cnt) {
-          const uint4 u = *(const uint4*)(e + (size_t)eid * H + col);
-          const T* v = (const T*)&u;
+          float v[V];
+          P::unpack16(*(const uint4*)(e + (size_t)eid * H + col), v);
 #pragma unroll
-          for (int q = 0; q < V; ++q) acc[q] += (float)v[q];
+          for (int q = 0; q < V; ++q) acc[q] += v[q];
         }
       }
     }
@@ -653,10 +660,14 @@ int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* sr
                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool src_sorted) {
   if (n <= 0) return 0;
   const bool f32 = prec == TRK_PREC_F32;
+  // split BF16 stores the same fragment blocks per k block as BF16
   const bool ok = net.H == 128 ? (f32 ? gnn_shapes_ok<PrecF32, 128>(net) : gnn_shapes_ok<PrecBF16, 128>(net))
                                : (f32 ? gnn_shapes_ok<PrecF32, 32>(net) : gnn_shapes_ok<PrecBF16, 32>(net));
   if (!ok) return -1;
-  if (prec == TRK_PREC_F32) {
+  if (prec == TRK_PREC_X3) {
+    if (net.H == 128) { run_gnn128<PrecX3>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+    if (net.H == 32) { run_gnn<PrecX3, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+  } else if (prec == TRK_PREC_F32) {
     if (net.H == 128) { run_gnn128<PrecF32>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
     if (net.H == 32) { run_gnn<PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
   } else {

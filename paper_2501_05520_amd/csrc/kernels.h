@@ -4,7 +4,8 @@
 #include <stdint.h>
 #include "layers.h"
 
-enum { TRK_PREC_F32 = 0, TRK_PREC_BF16 = 1, TRK_PREC_FP8 = 2 };
+// layer precisions (split BF16: FP32 values carried as two BF16 parts, see PrecX3)
+enum { TRK_PREC_F32 = 0, TRK_PREC_BF16 = 1, TRK_PREC_FP8 = 2, TRK_PREC_X3 = 3 };
 // bits of the device error word
 enum { TRK_ERRBIT_CAPACITY = 1, TRK_ERRBIT_INDEX = 2 };
 
@@ -101,3 +102,8 @@ int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* sr
 // segmented rank sort of unique int keys: for each segment [ptr[i], ptr[i+1]) of in, writes the
 // keys ascending to out at the same positions.  n segments (from d_n if given).
 void launch_segment_sort(const int* ptr, const int* in, int* out, int n, hipStream_t s);
+
+// ---- fit.hip ----
+// blocks of the stable radix sort that groups up to n hits by label
+constexpr int FIT_SORT_CHUNK = 2048;
+inline int64_t fit_sort_blocks(int64_t n) { return (n + FIT_SORT_CHUNK - 1) / FIT_SORT_CHUNK; }

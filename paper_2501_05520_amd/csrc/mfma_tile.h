@@ -9,7 +9,9 @@
 //        g = l>>4 carries k = 16*kb + 4g + s in issue s = 0..3;
 //   BF16 (v_mfma_f32_16x16x32_bf16, 16 bytes): lane group g carries k = 32*kb + 8g + j, j = 0..7;
 //   FP8  (v_mfma_scale_f32_16x16x128_f8f6f4 in E4M3 mode with unit block scales,
-//        32 bytes): lane group g carries k = 128*kb + 32g + j, j = 0..31.
+//        32 bytes): lane group g carries k = 128*kb + 32g + j, j = 0..31;
+//   split BF16 (three v_mfma_f32_16x16x32_bf16 per block, 32 bytes): as BF16, the
+//        high parts of the eight values then their low parts.
 // Any assignment of k to (lane group, slot) is valid as long as the weight and the
 // activation fragments agree, which lets each lane read 16 contiguous bytes of its
 // activation row from LDS.  Weights are pre-arranged on the host into "fragment
@@ -52,6 +54,13 @@ struct PrecF32 {
   }
   static __device__ __forceinline__ float load1(const float* p) { return *p; }
   static __device__ __forceinline__ float cvt(float v) { return v; }
+  // element k of a row
+  static __device__ __forceinline__ void store1(float* row, int k, float v) { row[k] = v; }
+  // the values held by 16 bytes of a row
+  static constexpr int V16 = 4;
+  static __device__ __forceinline__ void unpack16(const uint4& u, float (&v)[V16]) {
+    v[0] = __uint_as_float(u.x); v[1] = __uint_as_float(u.y); v[2] = __uint_as_float(u.z); v[3] = __uint_as_float(u.w);
+  }
 };
 
 struct PrecBF16 {
@@ -75,6 +84,79 @@ struct PrecBF16 {
   }
   static __device__ __forceinline__ float load1(const __bf16* p) { return (float)*p; }
   static __device__ __forceinline__ __bf16 cvt(float v) { return (__bf16)v; }
+  static __device__ __forceinline__ void store1(__bf16* row, int k, float v) { row[k] = (__bf16)v; }
+  static constexpr int V16 = 8;
+  static __device__ __forceinline__ void unpack16(const uint4& u, float (&v)[V16]) {
+    const bf16x8 b = __builtin_bit_cast(bf16x8, u);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (float)b[q];
+  }
+};
+
+// Split BF16: a value v is held as hi = bf16(v) and lo = bf16(v - hi) (both
+// round-to-nearest-even): hi + lo is within 2^-18 of v relatively.  A product is
+// formed from three BF16 products, hi*hi + hi*lo + lo*hi, accumulated in FP32; the
+// dropped lo*lo term is below 2^-18 of the product, the order of the split's own
+// representation error.  This is the three-term
+// split of Henry, Tang and Heinecke (ARITH 2019), here on the BF16 matrix cores.
+// Storage: in every group of four consecutive elements of a row (16 bytes), the
+// four high parts, then the four low parts, so that 16-byte moves of a row move
+// whole elements.  One element is the 4-byte unit x3_t.
+struct x3_t {
+  uint32_t bits;
+};
+
+struct PrecX3 {
+  typedef x3_t act_t;
+  typedef i32x8 frag_t;
+  static constexpr int KB = 32;
+  static constexpr int PAD = 4;
+  static __device__ __forceinline__ void mma(f32x4& acc, const i32x8& w, const i32x8& x) {
+    const bf16x8 wh = __builtin_bit_cast(bf16x8, __builtin_shufflevector(w, w, 0, 1, 2, 3));
+    const bf16x8 wl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(w, w, 4, 5, 6, 7));
+    const bf16x8 xh = __builtin_bit_cast(bf16x8, __builtin_shufflevector(x, x, 0, 1, 2, 3));
+    const bf16x8 xl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(x, x, 4, 5, 6, 7));
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, acc, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void mma_first(f32x4& acc, const i32x8& w, const i32x8& x) {
+    const bf16x8 wh = __builtin_bit_cast(bf16x8, __builtin_shufflevector(w, w, 0, 1, 2, 3));
+    const bf16x8 wl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(w, w, 4, 5, 6, 7));
+    const bf16x8 xh = __builtin_bit_cast(bf16x8, __builtin_shufflevector(x, x, 0, 1, 2, 3));
+    const bf16x8 xl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(x, x, 4, 5, 6, 7));
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, acc, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void split(float v, __bf16& h, __bf16& l) {
+    h = (__bf16)v;
+    l = (__bf16)(v - (float)h);
+  }
+  // four consecutive elements starting at a multiple of four
+  static __device__ __forceinline__ void store4(x3_t* p, float a, float b, float c, float d) {
+    bf16x4 h, l;
+    __bf16 t0, t1;
+    split(a, t0, t1); h[0] = t0; l[0] = t1;
+    split(b, t0, t1); h[1] = t0; l[1] = t1;
+    split(c, t0, t1); h[2] = t0; l[2] = t1;
+    split(d, t0, t1); h[3] = t0; l[3] = t1;
+    const uint2 hu = __builtin_bit_cast(uint2, h), lu = __builtin_bit_cast(uint2, l);
+    *(uint4*)p = make_uint4(hu.x, hu.y, lu.x, lu.y);
+  }
+  static __device__ __forceinline__ void store1(x3_t* row, int k, float v) {
+    __bf16* q = (__bf16*)(row + (k & ~3));
+    __bf16 h, l;
+    split(v, h, l);
+    q[k & 3] = h;
+    q[4 + (k & 3)] = l;
+  }
+  static constexpr int V16 = 4;
+  static __device__ __forceinline__ void unpack16(const uint4& u, float (&v)[V16]) {
+    const bf16x8 b = __builtin_bit_cast(bf16x8, u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (float)b[q] + (float)b[4 + q];
+  }
 };
 
 // OCP FP8 E4M3 (max 448).  Activations are tanh outputs (|a| <= 1) stored as
@@ -102,7 +184,11 @@ struct PrecFP8 {
 
 template <class P>
 __device__ __forceinline__ typename P::frag_t load_frag(const typename P::act_t* p) {
-  if constexpr (sizeof(typename P::frag_t) == 16) {
+  if constexpr (std::is_same<P, PrecX3>::value) {
+    // eight elements = two 16-byte groups (hi0..3 lo0..3, hi4..7 lo4..7)
+    const uint4 a = *(const uint4*)p, b = *(const uint4*)(p + 4);
+    return i32x8{(int)a.x, (int)a.y, (int)b.x, (int)b.y, (int)a.z, (int)a.w, (int)b.z, (int)b.w};
+  } else if constexpr (sizeof(typename P::frag_t) == 16) {
     return *(const uint4*)p;
   } else {
     const uint4 a = *(const uint4*)p, b = *(const uint4*)(p + 16);

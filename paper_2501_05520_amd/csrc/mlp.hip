@@ -9,7 +9,8 @@
 // P is the precision of the square hidden layers (and of the embedding's output
 // layer); P0 that of the narrow first layer (K = 3 or 2 * emb_dim), which is the
 // same except in FP8 mode, where the first layer runs in BF16 because an FP8
-// product consumes k in blocks of 128.
+// product consumes k in blocks of 128, and in split-BF16 mode, where it runs in
+// FP32 (one k block either way).
 #include "kernels.h"
 #include "mfma_tile.h"
 #include <stdlib.h>
@@ -213,6 +214,9 @@ int launch_embed(int prec, int W, const float* x, int n, const DevLayer& l_in, c
     if (W == 1024 && tile_variant() == 2) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 8>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
     if (W == 1024) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
     if (W == 64) { launch_embed_t<PrecF32, PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
+  } else if (prec == TRK_PREC_X3) {
+    if (W == 1024) { launch_embed_t<PrecX3, PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 64) { launch_embed_t<PrecX3, PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {
     if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecFP8, PrecBF16, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
     if (W == 1024) { launch_embed_t<PrecFP8, PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
@@ -232,6 +236,9 @@ int launch_filter(int prec, int W, const float* emb, int D, const int* src, cons
     if (W == 512 && tile_variant() == 2) { launch_filter_t<PrecF32, PrecF32, 512, 32, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 512) { launch_filter_t<PrecF32, PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 64) { launch_filter_t<PrecF32, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
+  } else if (prec == TRK_PREC_X3) {
+    if (W == 512) { launch_filter_t<PrecX3, PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 64) { launch_filter_t<PrecX3, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {
     if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 512) { launch_filter_t<PrecFP8, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }

@@ -34,13 +34,21 @@ uint16_t host_f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
+float host_bf2f(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
 constexpr float FP8_ACT_SCALE = 256.f;   // storage scale of FP8 activations (|tanh| <= 1)
 
 // fragment blocks of W[K][N]: block (nt, kb) at index nt * nkb + kb, 64 lanes x
-// 16 bytes (FP32, BF16) or 32 bytes (FP8, values w * scale).
+// 16 bytes (FP32, BF16) or 32 bytes (FP8, values w * scale; split BF16, the high
+// then the low parts).
 std::vector<uint8_t> make_fragments(const float* w, int K, int N, int prec, int& nkb, int& nnt, float scale = 1.f) {
-  const int KB = prec == TRK_PREC_F32 ? 16 : prec == TRK_PREC_BF16 ? 32 : 128;
-  const int FB = prec == TRK_PREC_FP8 ? 32 : 16;
+  const int KB = prec == TRK_PREC_F32 ? 16 : (prec == TRK_PREC_BF16 || prec == TRK_PREC_X3) ? 32 : 128;
+  const int FB = (prec == TRK_PREC_FP8 || prec == TRK_PREC_X3) ? 32 : 16;
   nkb = (K + KB - 1) / KB;
   nnt = (N + 15) / 16;
   std::vector<uint8_t> out((size_t)nkb * nnt * 64 * FB, 0);
@@ -61,6 +69,16 @@ std::vector<uint8_t> make_fragments(const float* w, int K, int N, int prec, int&
             v[s] = (k < K && n < N) ? w[(size_t)k * N + n] : 0.f;
           }
           memcpy(dstp, v, 16);
+        } else if (prec == TRK_PREC_X3) {
+          // the eight high parts, then the eight low parts
+          uint16_t v[16];
+          for (int j = 0; j < 8; ++j) {
+            const int k = kb * 32 + 8 * g + j;
+            const float x = (k < K && n < N) ? w[(size_t)k * N + n] : 0.f;
+            v[j] = host_f2bf(x);
+            v[8 + j] = host_f2bf(x - host_bf2f(v[j]));
+          }
+          memcpy(dstp, v, 32);
         } else {
           uint16_t v[8];
           for (int j = 0; j < 8; ++j) {
@@ -90,7 +108,7 @@ int validate_config(const trk_config* c) {
   if (!width_ok(c->filt_hidden, {64, 512}) || c->filt_layers < 1 || c->filt_layers > 7) return TRK_E_INVAL;
   if (!width_ok(c->gnn_hidden, {32, 128}) || c->gnn_iters < 0 || c->gnn_iters > 64) return TRK_E_INVAL;
   if (!(c->radius > 0.f) || c->k_max < 1 || c->k_max > 1024) return TRK_E_INVAL;
-  if (c->precision < TRK_FP32 || c->precision > TRK_BF16_EMB32) return TRK_E_INVAL;
+  if (c->precision < TRK_FP32 || c->precision > TRK_BF16X3) return TRK_E_INVAL;
   if ((c->precision == TRK_FP8 || c->precision == TRK_FP8_ALL) && (c->emb_hidden % 128 || c->filt_hidden % 128))
     return TRK_E_INVAL;
   if (c->max_hits < 1 || c->max_hits > (1LL << 30)) return TRK_E_INVAL;
@@ -219,9 +237,10 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   const int prec = c->prec, prec_emb = c->prec_emb;
   // FP8 modes: FP8 for the layers that read a hidden activation tile of an FP8
   // MLP, BF16 for the narrow first layers and for the whole interaction network
-  const int prec_in = prec == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec;
-  const int prec_emb_in = prec_emb == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec_emb;
-  const int prec_gnn = prec_in;
+  // (split BF16: FP32 for the narrow first MLP layers)
+  const int prec_in = prec == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec == TRK_PREC_X3 ? TRK_PREC_F32 : prec;
+  const int prec_emb_in = prec_emb == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec_emb == TRK_PREC_X3 ? TRK_PREC_F32 : prec_emb;
+  const int prec_gnn = prec == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec;
   WeightUpload up;
   up.layer(c->emb_in, emb[0], prec_emb_in);
   c->emb_hid.n = k.emb_layers - 1;
@@ -262,13 +281,14 @@ int alloc_scratch(trk_ctx* c) {
   const trk_config& k = c->cfg;
   const int64_t NH = k.max_hits, CC = k.max_cand_edges, CF = k.max_kept_edges;
   const int H = k.gnn_hidden;
-  const size_t act = c->prec == TRK_PREC_F32 ? 4 : 2;
+  const size_t act = (c->prec == TRK_PREC_F32 || c->prec == TRK_PREC_X3) ? 4 : 2;
   Arena& a = c->arena;
   GraphScratch& g = c->graph;
   GnnScratch& s = c->gs;
   g.table = next_pow2(2 * NH);
   g.stats_blocks = 256;
-  const int64_t tmp_ints = std::max({scan_tmp_ints(CC), scan_tmp_ints(CF), scan_tmp_ints(g.table), scan_tmp_ints(NH + 1)});
+  const int64_t tmp_ints = std::max({scan_tmp_ints(CC), scan_tmp_ints(CF), scan_tmp_ints(g.table), scan_tmp_ints(NH + 1),
+                                     scan_tmp_ints(256 * fit_sort_blocks(NH))});
   a.add(c->emb, (size_t)NH * k.emb_dim);
   a.add(c->cand_src, CC);
   a.add(c->cand_dst, CC);
@@ -281,9 +301,12 @@ int alloc_scratch(trk_ctx* c) {
   a.add(c->fit_flag, NH + 1);
   a.add(c->fit_cidx, NH + 1);
   a.add(c->fit_start, NH + 1);
-  a.add(c->fit_cursor, NH);
+  a.add(c->fit_keys, NH);
+  a.add(c->fit_keys2, NH);
   a.add(c->fit_raw, NH);
   a.add(c->fit_hits, NH);
+  a.add(c->fit_hist, (size_t)256 * fit_sort_blocks(NH) + 1);
+  a.add(c->fit_hoff, (size_t)256 * fit_sort_blocks(NH) + 1);
   a.add(c->offs, (size_t)k.max_events + 1);
   a.add(c->dev_words, 16);
   a.add(c->batch_counts, (size_t)k.max_events * 4);
@@ -425,6 +448,7 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
     case TRK_FP8: c->prec = TRK_PREC_FP8; c->prec_emb = TRK_PREC_BF16; break;
     case TRK_FP8_ALL: c->prec = c->prec_emb = TRK_PREC_FP8; break;
     case TRK_BF16_EMB32: c->prec = TRK_PREC_BF16; c->prec_emb = TRK_PREC_F32; break;
+    case TRK_BF16X3: c->prec = c->prec_emb = TRK_PREC_X3; break;
     default: c->prec = c->prec_emb = TRK_PREC_F32;
   }
   hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_id);

@@ -1,0 +1,136 @@
+"""GPU parity of the split-BF16 mode (TRK_BF16X3: every product formed on the
+BF16 matrix cores from the high and low BF16 parts of FP32 values) against the
+FP64 oracle, held to the FP32 bars: scores within 1e-4, labels identical away
+from the cuts.  The embedding carries the split's own error (each operand within
+2^-18 relatively, against 2^-24 for FP32), so it gets a looser bound, and the
+candidate graph is compared on the oracle's own embedding (stage-isolated).  At
+pile-up 200 the chain's labels are compared with the FP32 chain's."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gen import TINY, MU200, make_weights, generate_event
+from tests.gpu_helpers import compare_edges, label_agreement
+
+pytestmark = pytest.mark.gpu
+
+SCORE_TOL = 1e-4
+# split operands carry 2^-18 relative error each, so a product term is off by at most
+# about 3 * 2^-18 = 1.1e-5 of |w x|; a 1024-term sum of random-sign terms is about
+# sqrt(1024) / 3 ~ 10 times smaller than the sum of its magnitudes, which puts the
+# error of a wide layer's output near 1e-4 of its value in the worst case
+EMB_TOL = 2e-4
+SEEDS = [1, 2, 3, 4]
+
+
+@pytest.fixture(scope="module")
+def tiny_nets():
+    return make_weights(TINY, 0)
+
+
+@pytest.fixture(scope="module")
+def tiny_pipe(tiny_nets):
+    from paper_2501_05520_amd.trk import Pipeline
+    p = Pipeline(TINY, tiny_nets, "bf16x3", max_hits=8192, max_events=4)
+    yield p
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def tiny_ref(tiny_nets):
+    out = {}
+    for s in SEEDS:
+        ev = generate_event(s, 1)
+        out[s] = (ev, oracle.event(ev.x, tiny_nets, TINY))
+    return out
+
+
+def _margin(r, cfg, tol):
+    return int(np.sum(np.abs(r["filter_scores"] - cfg.filter_cut) <= tol)) + \
+        int(np.sum(np.abs(r["gnn_scores"] - cfg.score_cut) <= tol))
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_tiny_stages(tiny_pipe, tiny_ref, tiny_nets, seed):
+    ev, r = tiny_ref[seed]
+    emb = tiny_pipe.embed(ev.x).cpu().numpy()
+    de = np.abs(emb - r["emb"]) / np.maximum(1.0, np.abs(r["emb"]))
+    assert de.max() <= EMB_TOL, de.max()
+    e32 = r["emb"].astype(np.float32)
+    p = tiny_pipe.filter(e32, r["src"], r["dst"])[0].cpu().numpy()
+    assert np.abs(p - r["filter_scores"]).max() <= SCORE_TOL
+    q = tiny_pipe.gnn(ev.x, r["fsrc"], r["fdst"]).cpu().numpy()
+    assert np.abs(q - r["gnn_scores"]).max() <= SCORE_TOL
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_tiny_end_to_end(tiny_pipe, tiny_ref, seed):
+    ev, r = tiny_ref[seed]
+    labels, info = tiny_pipe.event(ev.x)
+    labels = labels.cpu().numpy()
+    e32 = r["emb"].astype(np.float32)
+    rad = float(np.float32(TINY.radius))
+    lo, hi, d2 = oracle.radius_pairs(e32, rad)
+    # the chain's graph is built on its own embedding: edges may differ from the
+    # oracle's only for pairs within the embedding error of the radius or K-th distance
+    src, dst, _ = tiny_pipe.build_graph(tiny_pipe.embed(ev.x))
+    os_, od, _ = oracle.radius_graph(e32, rad, TINY.k_max)
+    ndiff, _, _ = compare_edges(e32, src.cpu().numpy(), dst.cpu().numpy(), os_, od, rad, TINY.k_max, lo, hi, d2)
+    if _margin(r, TINY, SCORE_TOL) == 0 and ndiff == 0:
+        assert np.array_equal(labels, r["labels"])
+    else:
+        hit, jac = label_agreement(labels, r["labels"])
+        assert hit >= 0.99
+
+
+@pytest.fixture(scope="module")
+def mid():
+    nets = make_weights(MU200, 0)
+    ev = generate_event(300, 10)
+    return nets, ev, oracle.event(ev.x, nets, MU200)
+
+
+def test_mid_stages_full_network(mid):
+    """Pile-up-10 event through the full-size network (embedding 3-1024x3-12, filter
+    24-512x3-1, H=128 T=8), every stage against the oracle."""
+    from paper_2501_05520_amd.trk import Pipeline
+    nets, ev, r = mid
+    p = Pipeline(MU200, nets, "bf16x3", max_hits=8192)
+    emb = p.embed(ev.x).cpu().numpy()
+    e32 = r["emb"].astype(np.float32)
+    pf = p.filter(e32, r["src"], r["dst"])[0].cpu().numpy()
+    q = p.gnn(ev.x, r["fsrc"], r["fdst"]).cpu().numpy()
+    labels, info = p.event(ev.x)
+    p.close()
+    de = np.abs(emb - r["emb"]) / np.maximum(1.0, np.abs(r["emb"]))
+    dpf, dq = np.abs(pf - r["filter_scores"]), np.abs(q - r["gnn_scores"])
+    hit, jac = label_agreement(labels.cpu().numpy(), r["labels"])
+    print(f"bf16x3 vs fp64 oracle: emb rel max {de.max():.3g}; filter |dp| max {dpf.max():.3g}; "
+          f"gnn |dp| max {dq.max():.3g}; cand edges {info['n_cand_edges']} (oracle {r['src'].size}); "
+          f"hit agreement {hit:.5f}")
+    assert de.max() <= EMB_TOL
+    assert dpf.max() <= SCORE_TOL and dq.max() <= SCORE_TOL
+    assert hit >= 0.999
+
+
+def test_mu200_agrees_with_fp32():
+    """The pile-up-200 chain in split BF16 against the FP32 chain: the track-candidate
+    labels of at least 99.9 % of the hits are the same."""
+    from paper_2501_05520_amd.trk import Pipeline
+    nets = make_weights(MU200, 0)
+    ev = generate_event(200, MU200.n_collisions)
+    p32 = Pipeline(MU200, nets, "fp32", max_hits=ev.n)
+    l32, i32 = p32.event(ev.x)
+    l32 = l32.cpu().numpy()
+    p32.close()
+    px = Pipeline(MU200, nets, "bf16x3", max_hits=ev.n)
+    lx, ix = px.event(ev.x)
+    lx2, _ = px.event(ev.x)
+    px.close()
+    assert torch.equal(lx, lx2)
+    hit, jac = label_agreement(lx.cpu().numpy(), l32)
+    print(f"bf16x3 vs fp32 at mu=200: cand edges {ix['n_cand_edges']} vs {i32['n_cand_edges']}, filtered "
+          f"{ix['n_filt_edges']} vs {i32['n_filt_edges']}, kept {ix['n_kept_edges']} vs {i32['n_kept_edges']}; "
+          f"hit agreement {hit:.5f} jaccard {jac:.4f}")
+    assert hit >= 0.999
