@@ -14,7 +14,8 @@
 // Selection and canonical edges.  Point i selects the k_max nearest points j != i
 // with d^2 < r^2 (FP32 squared distance, summed over dimensions in fixed order,
 // hence bitwise symmetric), ordered by the 64-bit key (bits(d^2) << 32 | j).
-// For saturated points the k_max-th key is found by an 8-pass radix select.  The
+// For saturated points the k_max-th key is found by an 8-pass radix select (over
+// the keys staged in LDS when they fit).  The
 // candidate edge set is the union of the selections as pairs (min, max):
 //   pass 2 counts each pair once - point i owns (i, j) when it selects j > i, and
 //          (j, i) when it selects j < i that does not select it back;
@@ -298,63 +299,92 @@ __device__ __forceinline__ void load_query(const QueryCtx& qc, int64_t q, int& i
   }
 }
 
+// k_max-th smallest of a wave's keys by radix select, 8 bits per pass from the top.
+// visit(g) calls g(key) for every key (per lane, any number of times per lane);
+// hist is the wave's 256-bin LDS histogram.
+template <class V>
+__device__ __forceinline__ unsigned long long radix_select(int (&hist)[256], int k_max, V&& visit) {
+  const int l = lane_id();
+  unsigned long long prefix = 0;
+  int rank = k_max - 1;
+  for (int p = 0; p < 8; ++p) {
+    const int shift = 56 - 8 * p;
+    const unsigned long long hmask = p == 0 ? 0ull : (~0ull << (shift + 8));
+    for (int b = l; b < 256; b += 64) hist[b] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    visit([&](unsigned long long k) {
+      if ((k & hmask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
+    });
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane l holds bins 4l .. 4l+3
+    const int h0 = hist[4 * l], h1 = hist[4 * l + 1], h2 = hist[4 * l + 2], h3 = hist[4 * l + 3];
+    const int s4 = h0 + h1 + h2 + h3;
+    const int incl = wave_incl_scan(s4);
+    const int excl = incl - s4;
+    int digit = -1, below = 0;
+    if (rank >= excl && rank < incl) {
+      int cum = excl;
+      if (rank < cum + h0) { digit = 4 * l; below = cum; }
+      else if (rank < cum + h0 + h1) { digit = 4 * l + 1; below = cum + h0; }
+      else if (rank < cum + h0 + h1 + h2) { digit = 4 * l + 2; below = cum + h0 + h1; }
+      else { digit = 4 * l + 3; below = cum + h0 + h1 + h2; }
+    }
+    const unsigned long long m = ballot(digit >= 0);
+    const int src_lane = __ffsll((long long)m) - 1;
+    digit = __shfl(digit, src_lane, 64);
+    below = __shfl(below, src_lane, 64);
+    prefix |= (unsigned long long)digit << shift;
+    rank -= below;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  return prefix;
+}
+
+// The within-r keys of a point are compacted into LDS during its counting pass
+// (up to SEL_CAP of them), so that a saturated point's select reads LDS; a point
+// with more neighbours than that enumerates its cells again in every select pass.
+constexpr int SEL_CAP = 512;
+
 // pass 1: within-r count and, for saturated points, the k_max-th selection key
 __global__ __launch_bounds__(QW * 64) void query_count_kernel(QueryCtx qc, int n, int k_max, int* __restrict__ cnt,
                                                               unsigned long long* __restrict__ thr,
                                                               int* __restrict__ counters) {
   __shared__ WaveSlots slots[QW];
   __shared__ int hist[QW][256];
+  __shared__ unsigned long long selk[QW][SEL_CAP];
   const int w = threadIdx.x >> 6, l = lane_id();
   FOR_QUERIES(q, n) {
     int i;
     unsigned long long qcell;
     float qe[EP];
     load_query(qc, q, i, qcell, qe);
-    int c = 0;
-    for_neighbours(qc, slots[w], i, qcell, qe, [&](int, float, bool ok) { c += ok ? 1 : 0; });
-    c = wave_sum(c);
+    int c = 0;   // wave-uniform running count
+    for_neighbours(qc, slots[w], i, qcell, qe, [&](int j, float d2, bool ok) {
+      const unsigned long long m = ballot(ok);
+      const int pos = c + mask_rank(m);
+      if (ok && pos < SEL_CAP) selk[w][pos] = sel_key(d2, j);
+      c += __popcll(m);
+    });
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     unsigned long long t = ~0ull;
-    if (c > k_max) {
-      // radix select of the k_max-th smallest key, 8 bits per pass from the top
-      unsigned long long prefix = 0;
-      int rank = k_max - 1;
-      for (int p = 0; p < 8; ++p) {
-        const int shift = 56 - 8 * p;
-        const unsigned long long hmask = p == 0 ? 0ull : (~0ull << (shift + 8));
-        for (int b = l; b < 256; b += 64) hist[w][b] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (c > k_max && c <= SEL_CAP) {
+      t = radix_select(hist[w], k_max, [&](auto&& g) {
+        for (int b = l; b < c; b += 64) g(selk[w][b]);
+      });
+    } else if (c > k_max) {
+      t = radix_select(hist[w], k_max, [&](auto&& g) {
         for_neighbours(qc, slots[w], i, qcell, qe, [&](int j, float d2, bool ok) {
-          if (ok) {
-            const unsigned long long k = sel_key(d2, j);
-            if ((k & hmask) == prefix) atomicAdd(&hist[w][(k >> shift) & 255], 1);
-          }
+          if (ok) g(sel_key(d2, j));
         });
-        // lane l holds bins 4l .. 4l+3
-        const int h0 = hist[w][4 * l], h1 = hist[w][4 * l + 1], h2 = hist[w][4 * l + 2], h3 = hist[w][4 * l + 3];
-        const int s4 = h0 + h1 + h2 + h3;
-        const int incl = wave_incl_scan(s4);
-        const int excl = incl - s4;
-        int digit = -1, below = 0;
-        if (rank >= excl && rank < incl) {
-          int cum = excl;
-          if (rank < cum + h0) { digit = 4 * l; below = cum; }
-          else if (rank < cum + h0 + h1) { digit = 4 * l + 1; below = cum + h0; }
-          else if (rank < cum + h0 + h1 + h2) { digit = 4 * l + 2; below = cum + h0 + h1; }
-          else { digit = 4 * l + 3; below = cum + h0 + h1 + h2; }
-        }
-        const unsigned long long m = ballot(digit >= 0);
-        const int src_lane = __ffsll((long long)m) - 1;
-        digit = __shfl(digit, src_lane, 64);
-        below = __shfl(below, src_lane, 64);
-        prefix |= (unsigned long long)digit << shift;
-        rank -= below;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-      t = prefix;
+      });
     }
     if (l == 0) {
       cnt[i] = c;
