@@ -29,7 +29,7 @@ GNN_FLOP_NODE_ITER = 2 * (2 * GNN_H * GNN_H + GNN_H * GNN_H + GNN_H * 2 * GNN_H)
 GNN_FLOP_EDGE_ONCE = 2 * (6 * GNN_H + GNN_H * GNN_H) + 2 * (GNN_H * GNN_H + GNN_H)  # edge encoder, output head
 GNN_FLOP_NODE_ONCE = 2 * (3 * GNN_H + GNN_H * GNN_H + GNN_H * 2 * GNN_H)            # node encoder + projections
 HBM_PEAK_GBS = 8000.0
-ACT_BYTES = {"fp32": 4, "bf16": 2, "fp8": 2, "fp8all": 2, "bf16emb32": 2, "bf16x3": 4}
+ACT_BYTES = {"fp32": 4, "bf16": 2, "fp8": 2, "fp8all": 2, "bf16emb32": 2, "bf16x3": 4, "bf16x3gnn16": 2}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_kernel_mu200_traffic.md")
@@ -89,7 +89,7 @@ def stage_rooflines(st, counts, prec, peak):
 # split BF16 issues three BF16 products per algorithmic product: its fraction is of
 # the BF16 peak counted in algorithmic FLOPs (at most 1/3)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp8all": 5000.0, "bf16emb32": 2500.0,
-               "bf16x3": 2500.0}
+               "bf16x3": 2500.0, "bf16x3gnn16": 2500.0}
 EVENT_SEEDS = list(range(200, 210))
 
 
@@ -98,7 +98,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "fp8all", "bf16emb32", "bf16x3"])
+    p.add_argument("--precision", default="fp32", choices=list(PEAK_TFLOPS))
     p.add_argument("--no-variant", action="store_true", help="skip the BF16 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--events", type=int, default=len(EVENT_SEEDS))
@@ -420,7 +420,7 @@ def main():
         "metric": "events/s and p50/p99 latency per mu=200 event; per-stage MFMA/HBM roofline %",
         "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3", "fp8all": "fp8-e4m3", "bf16emb32": "bf16", "bf16x3": "bf16x3"}[args.precision],
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3", "fp8all": "fp8-e4m3", "bf16emb32": "bf16", "bf16x3": "bf16x3", "bf16x3gnn16": "bf16x3+bf16"}[args.precision],
         "data": "synthetic helical-track events (seeded), random-init weights (seed 0)",
         "config": {"workload": "mu200 event: 110000 hits, emb 3-1024x3-12, r=0.2 K=256, filter 24-512x3-1, "
                                "IN H=128 T=8, trk_event per event", "events": len(xs),
@@ -441,7 +441,7 @@ def main():
     result["stage_roofline"] = stage_rooflines(st, result["counts"], args.precision, peak)
     if not args.no_variant:
         result["variants"] = {}
-        for other in [p for p in ("fp32", "bf16", "bf16emb32", "bf16x3", "fp8", "fp8all") if p != args.precision]:
+        for other in [p for p in ("fp32", "bf16", "bf16emb32", "bf16x3", "bf16x3gnn16", "fp8", "fp8all") if p != args.precision]:
             w2, lat2, inf2, lab2 = run_precision(other, cfg, nets, xs, args.steps, args.warmup, torch, trk)
             agr = [agreement(a, b) for a, b in zip(labels, lab2)]
             st2 = stage_means(inf2)
@@ -471,9 +471,12 @@ def main():
         # buffers, PCIe included; Poisson arrivals queue, the FP32 figure is back to
         # back) and the saturated rate beside the FP32 rate.  Three slots overlap
         # events on the device (throughput); one slot runs them one after another.
+        # The FP32 pipeline served at half its own rate gives its queueing tail under
+        # the same arrivals.
         result["serving_mu200"] = []
         for prec, slots, frac in (("bf16", 3, 1.0), ("bf16", 1, 1.0), ("bf16", 1, 0.5), ("bf16emb32", 1, 1.0),
-                                  ("bf16emb32", 1, 0.5), ("bf16x3", 1, 1.0), ("bf16x3", 1, 0.5)):
+                                  ("bf16emb32", 1, 0.5), ("bf16x3", 1, 1.0), ("bf16x3", 1, 0.5),
+                                  ("bf16x3gnn16", 1, 1.0), ("fp32", 1, 0.5)):
             try:
                 sv = serve_load(cfg, nets, prec, args.serve_seconds, 1.0, trk, mus=[200], rate=frac * value,
                                 n_slots=slots)

@@ -70,6 +70,8 @@ typedef enum {
                    * is carried as hi = bf16(v) plus lo = bf16(v - hi) (within 2^-18 of v) and a
                    * product is hi*hi + hi*lo + lo*hi with FP32 accumulation; activations are
                    * stored as the two parts (4 bytes).  The narrow first MLP layers run in FP32. */
+  TRK_BF16X3_GNN_BF16 = 6, /* embedding and filter as in TRK_BF16X3, the interaction network as in
+                            * TRK_BF16 (the score cut is the step least sensitive to precision) */
 } trk_precision;
 
 /* Model and sizing configuration, the analogue of a served model's config

@@ -41,8 +41,9 @@ struct trk_ctx {
   trk_config cfg;
   int device = 0;
   int n_cu = 256;
-  int prec = TRK_PREC_F32;       // filter MLP (and the interaction network unless FP8)
+  int prec = TRK_PREC_F32;       // filter MLP
   int prec_emb = TRK_PREC_F32;   // embedding MLP
+  int prec_gnn = TRK_PREC_F32;   // interaction network
   hipStream_t own_stream = nullptr;
   // weights
   void* wmem = nullptr;

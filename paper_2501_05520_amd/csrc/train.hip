@@ -589,7 +589,7 @@ void ew(K kernel, int64_t count, hipStream_t s, A... args) {
 // ---------------------------------------------------------------------------
 int train_create(trk_ctx* c) {
   const trk_config& k = c->cfg;
-  if (c->prec != TRK_PREC_F32) return TRK_E_INVAL;
+  if (c->prec != TRK_PREC_F32 || c->prec_emb != TRK_PREC_F32 || c->prec_gnn != TRK_PREC_F32) return TRK_E_INVAL;
   TrainState* T = new TrainState();
   c->train = T;
   offsets_for(k, *T);

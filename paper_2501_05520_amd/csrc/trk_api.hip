@@ -108,7 +108,7 @@ int validate_config(const trk_config* c) {
   if (!width_ok(c->filt_hidden, {64, 512}) || c->filt_layers < 1 || c->filt_layers > 7) return TRK_E_INVAL;
   if (!width_ok(c->gnn_hidden, {32, 128}) || c->gnn_iters < 0 || c->gnn_iters > 64) return TRK_E_INVAL;
   if (!(c->radius > 0.f) || c->k_max < 1 || c->k_max > 1024) return TRK_E_INVAL;
-  if (c->precision < TRK_FP32 || c->precision > TRK_BF16X3) return TRK_E_INVAL;
+  if (c->precision < TRK_FP32 || c->precision > TRK_BF16X3_GNN_BF16) return TRK_E_INVAL;
   if ((c->precision == TRK_FP8 || c->precision == TRK_FP8_ALL) && (c->emb_hidden % 128 || c->filt_hidden % 128))
     return TRK_E_INVAL;
   if (c->max_hits < 1 || c->max_hits > (1LL << 30)) return TRK_E_INVAL;
@@ -234,13 +234,12 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   rd.take(o1, 3 * H, H); rd.take(o2, H, 1);
   if (!rd.ok || rd.left != 0) return TRK_E_WEIGHTS;
 
-  const int prec = c->prec, prec_emb = c->prec_emb;
+  const int prec = c->prec, prec_emb = c->prec_emb, prec_gnn = c->prec_gnn;
   // FP8 modes: FP8 for the layers that read a hidden activation tile of an FP8
   // MLP, BF16 for the narrow first layers and for the whole interaction network
   // (split BF16: FP32 for the narrow first MLP layers)
   const int prec_in = prec == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec == TRK_PREC_X3 ? TRK_PREC_F32 : prec;
   const int prec_emb_in = prec_emb == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec_emb == TRK_PREC_X3 ? TRK_PREC_F32 : prec_emb;
-  const int prec_gnn = prec == TRK_PREC_FP8 ? TRK_PREC_BF16 : prec;
   WeightUpload up;
   up.layer(c->emb_in, emb[0], prec_emb_in);
   c->emb_hid.n = k.emb_layers - 1;
@@ -281,7 +280,7 @@ int alloc_scratch(trk_ctx* c) {
   const trk_config& k = c->cfg;
   const int64_t NH = k.max_hits, CC = k.max_cand_edges, CF = k.max_kept_edges;
   const int H = k.gnn_hidden;
-  const size_t act = (c->prec == TRK_PREC_F32 || c->prec == TRK_PREC_X3) ? 4 : 2;
+  const size_t act = (c->prec_gnn == TRK_PREC_F32 || c->prec_gnn == TRK_PREC_X3) ? 4 : 2;
   Arena& a = c->arena;
   GraphScratch& g = c->graph;
   GnnScratch& s = c->gs;
@@ -406,7 +405,7 @@ int run_chain(trk_ctx* c, const float* x, int n, const int* ev, int* labels, hip
                        c->filt_dst, k.max_kept_edges, n_filt, c->graph.tmp, s);
   mark(4);
   // the filtered edges keep the radius graph's (source, destination) order
-  if (launch_gnn(c->prec, c->gnn, x, n, c->filt_src, c->filt_dst, k.max_kept_edges, n_filt, c->gnn_scores, c->gs,
+  if (launch_gnn(c->prec_gnn, c->gnn, x, n, c->filt_src, c->filt_dst, k.max_kept_edges, n_filt, c->gnn_scores, c->gs,
                  c->n_cu, err, s, true))
     return TRK_E_INVAL;
   mark(5);
@@ -444,12 +443,14 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
   c->cfg = *cfg;
   c->device = device_id;
   switch (cfg->precision) {
-    case TRK_BF16: c->prec = c->prec_emb = TRK_PREC_BF16; break;
-    case TRK_FP8: c->prec = TRK_PREC_FP8; c->prec_emb = TRK_PREC_BF16; break;
-    case TRK_FP8_ALL: c->prec = c->prec_emb = TRK_PREC_FP8; break;
-    case TRK_BF16_EMB32: c->prec = TRK_PREC_BF16; c->prec_emb = TRK_PREC_F32; break;
-    case TRK_BF16X3: c->prec = c->prec_emb = TRK_PREC_X3; break;
-    default: c->prec = c->prec_emb = TRK_PREC_F32;
+    // (embedding, filter, interaction network)
+    case TRK_BF16: c->prec_emb = c->prec = c->prec_gnn = TRK_PREC_BF16; break;
+    case TRK_FP8: c->prec_emb = TRK_PREC_BF16; c->prec = TRK_PREC_FP8; c->prec_gnn = TRK_PREC_BF16; break;
+    case TRK_FP8_ALL: c->prec_emb = c->prec = TRK_PREC_FP8; c->prec_gnn = TRK_PREC_BF16; break;
+    case TRK_BF16_EMB32: c->prec_emb = TRK_PREC_F32; c->prec = c->prec_gnn = TRK_PREC_BF16; break;
+    case TRK_BF16X3: c->prec_emb = c->prec = c->prec_gnn = TRK_PREC_X3; break;
+    case TRK_BF16X3_GNN_BF16: c->prec_emb = c->prec = TRK_PREC_X3; c->prec_gnn = TRK_PREC_BF16; break;
+    default: c->prec_emb = c->prec = c->prec_gnn = TRK_PREC_F32;
   }
   hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_id);
   if (c->n_cu <= 0) c->n_cu = 256;
@@ -543,7 +544,7 @@ int trk_gnn(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const
   if (n == 0) return m == 0 ? TRK_OK : TRK_E_INVAL;
   DeviceGuard guard(c->device);
   launch_fill_int(c->dev_words, 0, 16, s);
-  if (launch_gnn(c->prec, c->gnn, d_x, (int)n, d_src, d_dst, m, nullptr, d_scores, c->gs, c->n_cu, &c->dev_words[0], s))
+  if (launch_gnn(c->prec_gnn, c->gnn, d_x, (int)n, d_src, d_dst, m, nullptr, d_scores, c->gs, c->n_cu, &c->dev_words[0], s))
     return TRK_E_INVAL;
   if (check_launch()) return TRK_E_DEVICE;
   if (sync_words(c, s)) return TRK_E_DEVICE;

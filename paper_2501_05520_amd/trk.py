@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("TRK_LIB") or os.path.join(_PKG, "libtrk.so")
 
 TRK_ABI_VERSION = 1
 TRK_WEIGHTS_MAGIC = 0x5754524B
-TRK_FP32, TRK_BF16, TRK_FP8, TRK_FP8_ALL, TRK_BF16_EMB32, TRK_BF16X3 = 0, 1, 2, 3, 4, 5
+TRK_FP32, TRK_BF16, TRK_FP8, TRK_FP8_ALL, TRK_BF16_EMB32, TRK_BF16X3, TRK_BF16X3_GNN_BF16 = range(7)
 STATUS = {0: "TRK_OK", -1: "TRK_E_INVAL", -2: "TRK_E_NOMEM", -3: "TRK_E_CAPACITY",
           -4: "TRK_E_DEVICE", -5: "TRK_E_WEIGHTS", -7: "TRK_E_EXPIRED", -8: "TRK_E_SHUTDOWN"}
 EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_filter", "trk_gnn",
@@ -161,7 +161,8 @@ def make_config(cfg, precision=TRK_FP32, max_hits=None, max_cand_edges=None, max
     gnn_iters, radius, k_max, filter_cut, score_cut)."""
     if isinstance(precision, str):
         precision = {"fp32": TRK_FP32, "bf16": TRK_BF16, "fp8": TRK_FP8, "fp8all": TRK_FP8_ALL,
-                     "bf16emb32": TRK_BF16_EMB32, "bf16x3": TRK_BF16X3}[precision]
+                     "bf16emb32": TRK_BF16_EMB32, "bf16x3": TRK_BF16X3,
+                     "bf16x3gnn16": TRK_BF16X3_GNN_BF16}[precision]
     max_hits = int(max_hits)
     cand = int(max_cand_edges if max_cand_edges is not None else max_hits * cfg.k_max)
     kept = int(max_kept_edges if max_kept_edges is not None else cand)

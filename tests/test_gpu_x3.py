@@ -114,7 +114,25 @@ def test_mid_stages_full_network(mid):
     assert hit >= 0.999
 
 
-def test_mu200_agrees_with_fp32():
+def test_mid_mixed_mode_filter_at_fp32_bar(mid):
+    """TRK_BF16X3_GNN_BF16: embedding and filter in split BF16 (filter scores at the FP32
+    bar), the interaction network in BF16 (its error reported)."""
+    from paper_2501_05520_amd.trk import Pipeline
+    nets, ev, r = mid
+    p = Pipeline(MU200, nets, "bf16x3gnn16", max_hits=8192)
+    e32 = r["emb"].astype(np.float32)
+    pf = p.filter(e32, r["src"], r["dst"])[0].cpu().numpy()
+    q = p.gnn(ev.x, r["fsrc"], r["fdst"]).cpu().numpy()
+    p.close()
+    dpf, dq = np.abs(pf - r["filter_scores"]), np.abs(q - r["gnn_scores"])
+    print(f"bf16x3gnn16 vs fp64 oracle: filter |dp| max {dpf.max():.3g}; gnn |dp| max {dq.max():.3g} "
+          f"p99 {np.percentile(dq, 99):.3g}")
+    assert dpf.max() <= SCORE_TOL
+    assert dq.max() < 0.2
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x3gnn16"])
+def test_mu200_agrees_with_fp32(precision):
     """The pile-up-200 chain in split BF16 against the FP32 chain: the track-candidate
     labels of at least 99.9 % of the hits are the same."""
     from paper_2501_05520_amd.trk import Pipeline
@@ -124,13 +142,13 @@ def test_mu200_agrees_with_fp32():
     l32, i32 = p32.event(ev.x)
     l32 = l32.cpu().numpy()
     p32.close()
-    px = Pipeline(MU200, nets, "bf16x3", max_hits=ev.n)
+    px = Pipeline(MU200, nets, precision, max_hits=ev.n)
     lx, ix = px.event(ev.x)
     lx2, _ = px.event(ev.x)
     px.close()
     assert torch.equal(lx, lx2)
     hit, jac = label_agreement(lx.cpu().numpy(), l32)
-    print(f"bf16x3 vs fp32 at mu=200: cand edges {ix['n_cand_edges']} vs {i32['n_cand_edges']}, filtered "
+    print(f"{precision} vs fp32 at mu=200: cand edges {ix['n_cand_edges']} vs {i32['n_cand_edges']}, filtered "
           f"{ix['n_filt_edges']} vs {i32['n_filt_edges']}, kept {ix['n_kept_edges']} vs {i32['n_kept_edges']}; "
           f"hit agreement {hit:.5f} jaccard {jac:.4f}")
     assert hit >= 0.999

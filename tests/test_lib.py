@@ -56,8 +56,8 @@ def test_strerror():
 
 @pytest.mark.parametrize("field,value", [("abi_version", 99), ("emb_hidden", 100), ("emb_dim", 17),
                                          ("filt_hidden", 48), ("gnn_hidden", 64), ("k_max", 0),
-                                         ("radius", -1.0), ("precision", 7), ("max_hits", 0),
-                                         ("precision", 2), ("precision", 3), ("precision", 6)])
+                                         ("radius", -1.0), ("precision", 7), ("precision", -1), ("max_hits", 0),
+                                         ("precision", 2), ("precision", 3), ("precision", 9)])
 def test_create_rejects_bad_config(field, value):
     # (the FP8 precisions are rejected for the tiny widths, 64 not being a multiple of 128)
     from paper_2501_05520_amd import trk
