@@ -79,11 +79,13 @@ __device__ __forceinline__ void stage_rows(const typename P::act_t* __restrict__
 }
 
 // product of an LDS activation tile with a layer of compile-time fan-in K
-// (about eight weight fragments per lane in flight)
+// (about 128 bytes of weight fragments per lane in flight: eight 16-byte
+// fragments, four 32-byte ones)
 template <class P, int MTW, int NTW, int K, bool INIT = false>
 __device__ __forceinline__ void gemm_k(f32x4 (&acc)[MTW][NTW], const typename P::act_t* xs, int ldx,
                                        const DevLayer& L, int nt0) {
-  tile_gemm_k<P, MTW, NTW, (K + P::KB - 1) / P::KB, (NTW >= 8 ? 1 : 8 / NTW), INIT>(acc, xs, ldx, L.w, L.nkb, nt0);
+  constexpr int F = NTW * (int)(sizeof(typename P::frag_t) / 16);   // 16-byte units per k block
+  tile_gemm_k<P, MTW, NTW, (K + P::KB - 1) / P::KB, (F >= 8 ? 1 : 8 / F), INIT>(acc, xs, ldx, L.w, L.nkb, nt0);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,12 +566,15 @@ __global__ void incidence_fill(const int* __restrict__ key, int64_t m_cap, const
   }
 }
 
-// Grid of the aggregation: by default about one node per wave (waves that finish
-// early are replaced at once, which balances uneven degrees); TRK_GNN_AGG=1 gives
-// a persistent grid of one full-occupancy set of waves walking the nodes.
+// Grid of the aggregation: by default one node per wave up to 65536 four-wave
+// blocks (waves that finish early are replaced at once, which balances uneven
+// degrees; measured faster than two nodes per wave and than a persistent grid);
+// TRK_GNN_AGG=1 gives a persistent grid of one full-occupancy set of waves walking
+// the nodes, TRK_GNN_AGG=b > 1 a cap of b blocks.
 int agg_blocks(int n, int n_cu) {
   const char* v = getenv("TRK_GNN_AGG");
-  return blocks_for(n, 4, (v && atoi(v) == 1) ? n_cu * 8 : 16384);
+  const int a = v ? atoi(v) : 0;
+  return blocks_for(n, 4, a == 1 ? n_cu * 8 : a > 1 ? a : 65536);
 }
 
 // the unrolled products read ceil(K / KB) fragment blocks per n-tile of each layer
