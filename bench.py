@@ -314,7 +314,7 @@ def fit_measure(cfg, nets, ev, labels_chain, torch, trk, reps=5):
     return out
 
 
-def train_measure(cfg, nets, steps, torch, trk):
+def train_measure(cfg, nets, steps, torch, trk, precision="fp32"):
     """Training configuration: filter + interaction network on a fresh pile-up-200
     event per step (seeds 10000+step), BCE on generator truth, hand-written
     backward with per-iteration recomputation, Adam; edge sets from the FP32
@@ -324,7 +324,8 @@ def train_measure(cfg, nets, steps, torch, trk):
     from paper_2501_05520_amd.training import TrainContext, train_step, edge_truth
     pipe = trk.Pipeline(cfg, nets, "fp32", max_hits=120000)
     free0 = torch.cuda.mem_get_info()[0]
-    tc = TrainContext(cfg, nets, max_hits=120000, max_cand_edges=4_500_000, max_kept_edges=2_000_000)
+    tc = TrainContext(cfg, nets, max_hits=120000, max_cand_edges=4_500_000, max_kept_edges=2_000_000,
+                      precision=precision)
     held = free0 - torch.cuda.mem_get_info()[0]
     times, losses = [], []
     for k in range(steps + 1):
@@ -346,7 +347,10 @@ def train_measure(cfg, nets, steps, torch, trk):
     pipe.close()
     return {"steps": steps, "step_ms": round(float(np.mean(times)) * 1e3, 2) if times else None,
             "loss": losses, "n_cand_edges": int(cs.numel()), "n_filt_edges": int(fs.numel()),
-            "device_memory_gb": round(held / 2**30, 2), "precision": "fp32 (activations and master weights)"}
+            "device_memory_gb": round(held / 2**30, 2),
+            "precision": {"fp32": "fp32 (activations and master weights)",
+                          "bf16": "bf16 operands of every product, fp32 accumulation, fp32 master weights "
+                                  "and stored states"}[precision]}
 
 
 def cpu_baseline(cfg, nets, x):
@@ -502,6 +506,10 @@ def main():
             result["training"] = train_measure(cfg, nets, args.train_steps, torch, trk)
         except trk.TrkError as e:
             result["training"] = {"error": str(e)}
+        try:
+            result["training_bf16"] = train_measure(cfg, nets, args.train_steps, torch, trk, "bf16")
+        except trk.TrkError as e:
+            result["training_bf16"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, nets, xs[0])
     print(json.dumps(result), flush=True)

@@ -99,7 +99,7 @@ typedef struct {
   int64_t max_kept_edges;     /* capacity of filtered edges (GNN input) */
   int32_t max_events;         /* largest batch of trk_batch */
   int32_t stage_timing;       /* non-zero: trk_event / trk_batch time each stage with HIP events */
-  int32_t training;           /* non-zero: allocate the training buffers (FP32 precision only) */
+  int32_t training;           /* non-zero: allocate the training buffers (TRK_FP32 or TRK_BF16 only) */
 } trk_config;
 
 /* Per-call counts reported by trk_event / trk_batch (all host memory). */
@@ -281,8 +281,11 @@ int trk_service_start(trk_server* srv, const char* host, int port, trk_service**
 void trk_service_stop(trk_service* svc);
 
 /* ------------------------------------------------------------------------
- * Training of the filter MLP and the interaction network (FP32 contexts created
- * with training != 0).  Objective, a reading of the training configuration:
+ * Training of the filter MLP and the interaction network (contexts created with
+ * training != 0, precision TRK_FP32 or TRK_BF16; in a TRK_BF16 context every product
+ * of the forward and backward passes takes BF16 operands with FP32 accumulation,
+ * while parameters, gradients, Adam moments and stored states stay FP32).
+ * Objective, a reading of the training configuration:
  * binary cross-entropy with logits on truth labels, averaged over the candidate
  * edges (filter) and over the filtered edges (interaction network); the edge sets
  * are inputs held fixed.  Parameters live in one flat FP32 device vector: the

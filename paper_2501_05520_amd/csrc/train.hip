@@ -11,7 +11,15 @@
 // there, so activation memory is (T+1) state copies instead of every layer of
 // every iteration.
 //
-// Building blocks, all on MFMA (v_mfma_f32_16x16x4_f32) or plain vector code:
+// Precision: an FP32 context trains with FP32 products; a BF16 context (the
+// training configuration with BF16 activations) rounds the operands of every
+// product - activations, deltas and the weight copies - to BF16 on the way into
+// the matrix cores (v_mfma_f32_16x16x32_bf16) and accumulates in FP32; the master
+// parameters, the Adam moments, stored activations and the element-wise steps stay
+// FP32.
+//
+// Building blocks, all on MFMA (v_mfma_f32_16x16x4_f32 or the BF16 form) or plain
+// vector code:
 //   rowgemm : out[r][:] = epi(X[r][:] W) for a row-major X (epilogues: store,
 //             accumulate, +bias, tanh(+bias), times (1 - aux^2));
 //   wgrad   : G[K(+1)][N] += X^T D over all rows, split over row chunks, partial
@@ -93,26 +101,27 @@ __global__ void bias_fill_kernel(float* out, float* out_s, int nout, const float
 // ---------------------------------------------------------------------------
 constexpr int RG_NW = 4;
 
-template <int NTW, int RG_MT, int RG_KMAX>
+template <class P, int NTW, int RG_MT, int RG_KMAX>
 __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __restrict__ X, int ldx, int K, int64_t m,
                                                              DevLayer W, float* __restrict__ out, int ldo, int N,
                                                              int epi, const float* __restrict__ aux, int ldaux) {
-  constexpr int LDX = RG_KMAX + 4;
+  typedef typename P::act_t T;
+  constexpr int LDX = RG_KMAX + P::PAD;
   constexpr int MTW = RG_MT / 16;
-  __shared__ __align__(16) float xs[RG_MT * LDX];
+  __shared__ __align__(16) T xs[RG_MT * LDX];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
-  const int kpad = W.nkb * 16;
+  const int kpad = W.nkb * P::KB;
   const int64_t ntiles = (m + RG_MT - 1) / RG_MT;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * RG_MT;
     for (int idx = threadIdx.x; idx < RG_MT * kpad; idx += blockDim.x) {
       const int mm = idx / kpad, k = idx - mm * kpad;
-      xs[mm * LDX + k] = (row0 + mm < m && k < K) ? X[(size_t)(row0 + mm) * ldx + k] : 0.f;
+      xs[mm * LDX + k] = P::cvt((row0 + mm < m && k < K) ? X[(size_t)(row0 + mm) * ldx + k] : 0.f);
     }
     __syncthreads();
     for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
       f32x4 acc[MTW][NTW];
-            tile_gemm<PrecF32, MTW, NTW, true>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
+      tile_gemm<P, MTW, NTW, true>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
         const int n0 = (nt0 + j) * 16 + 4 * g;
@@ -195,6 +204,70 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X,
     __syncthreads();
   }
   // lane holds rows k = k0 + wave*16 + r, columns n = n0 + j*16 + 4g + c
+  const int k = k0 + wave * 16 + r;
+  if (k < Kb) {
+    float* P = partial + ((size_t)blockIdx.z * Kb + k) * N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int n = n0 + j * 16 + 4 * g + c;
+        if (n < N) P[n] = acc[j][c];
+      }
+  }
+}
+
+// The same partial products with BF16 operands: the staged rows are held
+// transposed (column-major, rows contiguous), so that a lane's eight consecutive
+// rows of one column are one 16-byte read; 32 rows per product.
+constexpr int WGB_LD = WG_R + 8;   // row stride of the transposed tiles (bf16 elements)
+
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(const float* __restrict__ X, int ldx,
+                                                         const int* __restrict__ gsrc, const int* __restrict__ gdst,
+                                                         const float* __restrict__ S, int gd, int gn, int K,
+                                                         int with_bias, const float* __restrict__ Dm, int ldd, int N,
+                                                         int64_t m, int64_t rows_per_chunk, float* __restrict__ partial) {
+  __shared__ __align__(16) __bf16 xt[WG_T][WGB_LD];
+  __shared__ __align__(16) __bf16 dt[WG_T][WGB_LD];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int k0 = blockIdx.x * WG_T, n0 = blockIdx.y * WG_T;
+  const int Kb = K + (with_bias ? 1 : 0);
+  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t rend = min(m, rbeg + rows_per_chunk);
+  f32x4 acc[4];
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
+    for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
+      const int rr = idx / WG_T, c = idx - rr * WG_T;
+      const int64_t row = rs + rr;
+      const int k = k0 + c, n = n0 + c;
+      float xv = 0.f, dv = 0.f;
+      if (row < rend) {
+        if (k < K) {
+          if (gsrc) xv = k < gd ? S[node_of(gsrc[row], gn) * gd + k] : S[node_of(gdst[row], gn) * gd + (k - gd)];
+          else xv = X[(size_t)row * ldx + k];
+        } else if (k == K && with_bias) {
+          xv = 1.f;
+        }
+        if (n < N) dv = Dm[(size_t)row * ldd + n];
+      }
+      xt[c][rr] = (__bf16)xv;
+      dt[c][rr] = (__bf16)dv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < WG_R; rr += 32) {
+      // A: D^T rows (n = j*16 + r), B: X^T columns (k = wave*16 + r); lane group g
+      // carries rows rr + 8g .. rr + 8g + 7
+      const bf16x8 xb = *(const bf16x8*)&xt[wave * 16 + r][rr + 8 * g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf16x8 da = *(const bf16x8*)&dt[j * 16 + r][rr + 8 * g];
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da, xb, acc[j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
   const int k = k0 + wave * 16 + r;
   if (k < Kb) {
     float* P = partial + ((size_t)blockIdx.z * Kb + k) * N;
@@ -410,8 +483,9 @@ struct LayerOff {
 
 struct TrainState {
   int64_t n_params = 0;
+  bool bf16 = false;   // BF16 operands for every product (a BF16 context)
   std::vector<LayerOff> filt, ne, ee, en, nn, out, emb;   // per network, per layer
-  // FP32 fragment blocks for the training products
+  // fragment blocks for the training products (FP32, or BF16 in a BF16 context)
   void* fmem = nullptr;
   std::vector<DevLayer> filtF;       // forward layers 0..L (last: K x 1)
   std::vector<DevLayer> filtT;       // transposed hidden layers 1..L-1 (index l -> W_l^T)
@@ -500,10 +574,11 @@ size_t frag_bytes(int K, int N) { return (size_t)((K + 15) / 16) * ((N + 15) / 1
 struct FragAlloc {
   std::vector<std::pair<DevLayer*, std::pair<int, int>>> req;
   size_t total = 0;
+  bool bf16 = false;   // BF16 blocks take k in 32s (the FP32 size is allocated either way)
   void add(DevLayer& L, int K, int N) {
     L.K = K;
     L.N = N;
-    L.nkb = (K + 15) / 16;
+    L.nkb = bf16 ? (K + 31) / 32 : (K + 15) / 16;
     L.nnt = (N + 15) / 16;
     req.push_back({&L, {K, N}});
     total += frag_bytes(K, N) + (size_t)L.nnt * 16 * 4 + 512;
@@ -536,26 +611,36 @@ MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
   return v;
 }
 
-template <int NTW>
+template <class P, int NTW>
 void rowgemm_t(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
                const float* aux, int ldaux, int n_cu, hipStream_t s) {
-  if (W.nkb * 16 <= 512) {
+  if (W.nkb * P::KB <= 512) {
     const int64_t tiles = (m + 63) / 64;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
-    if (grid > 0) rowgemm_kernel<NTW, 64, 512><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+    if (grid > 0)
+      rowgemm_kernel<P, NTW, 64, 512><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
   } else {
     const int64_t tiles = (m + 31) / 32;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
-    if (grid > 0) rowgemm_kernel<NTW, 32, 1024><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+    if (grid > 0)
+      rowgemm_kernel<P, NTW, 32, 1024><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
   }
 }
 
-void rowgemm(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
-             const float* aux, int ldaux, int n_cu, hipStream_t s) {
+template <class P>
+void rowgemm_p(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
+               const float* aux, int ldaux, int n_cu, hipStream_t s) {
   const int per_wave = (W.nnt + RG_NW - 1) / RG_NW;
-  if (per_wave <= 1) rowgemm_t<1>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
-  else if (per_wave <= 2) rowgemm_t<2>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
-  else rowgemm_t<4>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  if (per_wave <= 1) rowgemm_t<P, 1>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  else if (per_wave <= 2) rowgemm_t<P, 2>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  else rowgemm_t<P, 4>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+}
+
+// out = epi(X W) with W's blocks in the training precision (bf16: BF16 blocks)
+void rowgemm(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
+             const float* aux, int ldaux, int n_cu, hipStream_t s, bool bf16) {
+  if (bf16) rowgemm_p<PrecBF16>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  else rowgemm_p<PrecF32>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
 }
 
 void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int gn,
@@ -567,7 +652,11 @@ void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* g
   const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
   dim3 grid((Kb + WG_T - 1) / WG_T, (N + WG_T - 1) / WG_T, chunks);
   if (m > 0) {
-    wgrad_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N, m, rpc, T.partial);
+    if (T.bf16)
+      wgrad_bf16_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N, m, rpc,
+                                             T.partial);
+    else
+      wgrad_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N, m, rpc, T.partial);
     wgrad_reduce_kernel<<<blocks_for(count, 256), 256, 0, s>>>(T.partial, chunks, count, grad);
   }
 }
@@ -589,12 +678,16 @@ void ew(K kernel, int64_t count, hipStream_t s, A... args) {
 // ---------------------------------------------------------------------------
 int train_create(trk_ctx* c) {
   const trk_config& k = c->cfg;
-  if (c->prec != TRK_PREC_F32 || c->prec_emb != TRK_PREC_F32 || c->prec_gnn != TRK_PREC_F32) return TRK_E_INVAL;
+  const bool all_f32 = c->prec == TRK_PREC_F32 && c->prec_emb == TRK_PREC_F32 && c->prec_gnn == TRK_PREC_F32;
+  const bool all_bf16 = c->prec == TRK_PREC_BF16 && c->prec_emb == TRK_PREC_BF16 && c->prec_gnn == TRK_PREC_BF16;
+  if (!all_f32 && !all_bf16) return TRK_E_INVAL;
   TrainState* T = new TrainState();
   c->train = T;
+  T->bf16 = all_bf16;
   offsets_for(k, *T);
   const int H = k.gnn_hidden, F = k.filt_hidden, D = k.emb_dim, L = k.filt_layers;
   FragAlloc fa;
+  fa.bf16 = T->bf16;
   T->filtF.resize(L + 1);
   T->filtT.resize(L + 1);
   for (int i = 0; i <= L; ++i) fa.add(T->filtF[i], T->filt[i].K, T->filt[i].N);
@@ -667,47 +760,49 @@ int64_t train_param_count(const trk_config& k) {
   return T.n_params;
 }
 
-// Rebuilds every FP32 fragment block (forward, transposed, and the inference
-// layers of the context) from the flat parameter vector P (device).
+// Rebuilds every fragment block (forward, transposed, and the inference layers of
+// the context) from the flat parameter vector P (device).
 int train_set_params(trk_ctx* c, const float* P, hipStream_t s) {
   TrainState& T = *c->train;
   const int H = c->cfg.gnn_hidden, L = c->cfg.filt_layers;
   MatView none;
   for (int i = 0; i <= L; ++i) {
     const LayerOff& o = T.filt[i];
-    fill(T.filtF[i], o.K, o.N, view(P, o), none, 0, 0, P + o.b, 0, s);
-    if (i >= 1 && i < L) fill(T.filtT[i], o.N, o.K, view(P, o, 0, 1), none, 0, 0, nullptr, 0, s);
+    fill(T.filtF[i], o.K, o.N, view(P, o), none, 0, 0, P + o.b, T.bf16, s);
+    if (i >= 1 && i < L) fill(T.filtT[i], o.N, o.K, view(P, o, 0, 1), none, 0, 0, nullptr, T.bf16, s);
   }
-  fill(T.ne1, 3, H, view(P, T.ne[0]), none, 0, 0, P + T.ne[0].b, 0, s);
-  fill(T.ne2, H, H, view(P, T.ne[1]), none, 0, 0, P + T.ne[1].b, 0, s);
-  fill(T.ee1, 6, H, view(P, T.ee[0]), none, 0, 0, P + T.ee[0].b, 0, s);
-  fill(T.ee2, H, H, view(P, T.ee[1]), none, 0, 0, P + T.ee[1].b, 0, s);
-  fill(T.ec, H, H, view(P, T.en[0], 2 * H), none, 0, 0, P + T.en[0].b, 0, s);
-  fill(T.eab, H, 2 * H, view(P, T.en[0], 0), view(P, T.en[0], H), 1, H, nullptr, 0, s);
-  fill(T.e2, H, H, view(P, T.en[1]), none, 0, 0, P + T.en[1].b, 0, s);
-  fill(T.n1, 2 * H, H, view(P, T.nn[0]), none, 0, 0, P + T.nn[0].b, 0, s);
-  fill(T.n2, H, H, view(P, T.nn[1]), none, 0, 0, P + T.nn[1].b, 0, s);
-  fill(T.oc, H, H, view(P, T.out[0], 2 * H), none, 0, 0, P + T.out[0].b, 0, s);
-  fill(T.oab, H, 2 * H, view(P, T.out[0], 0), view(P, T.out[0], H), 1, H, nullptr, 0, s);
-  fill(T.o2, H, 1, view(P, T.out[1]), none, 0, 0, P + T.out[1].b, 0, s);
+  fill(T.ne1, 3, H, view(P, T.ne[0]), none, 0, 0, P + T.ne[0].b, T.bf16, s);
+  fill(T.ne2, H, H, view(P, T.ne[1]), none, 0, 0, P + T.ne[1].b, T.bf16, s);
+  fill(T.ee1, 6, H, view(P, T.ee[0]), none, 0, 0, P + T.ee[0].b, T.bf16, s);
+  fill(T.ee2, H, H, view(P, T.ee[1]), none, 0, 0, P + T.ee[1].b, T.bf16, s);
+  fill(T.ec, H, H, view(P, T.en[0], 2 * H), none, 0, 0, P + T.en[0].b, T.bf16, s);
+  fill(T.eab, H, 2 * H, view(P, T.en[0], 0), view(P, T.en[0], H), 1, H, nullptr, T.bf16, s);
+  fill(T.e2, H, H, view(P, T.en[1]), none, 0, 0, P + T.en[1].b, T.bf16, s);
+  fill(T.n1, 2 * H, H, view(P, T.nn[0]), none, 0, 0, P + T.nn[0].b, T.bf16, s);
+  fill(T.n2, H, H, view(P, T.nn[1]), none, 0, 0, P + T.nn[1].b, T.bf16, s);
+  fill(T.oc, H, H, view(P, T.out[0], 2 * H), none, 0, 0, P + T.out[0].b, T.bf16, s);
+  fill(T.oab, H, 2 * H, view(P, T.out[0], 0), view(P, T.out[0], H), 1, H, nullptr, T.bf16, s);
+  fill(T.o2, H, 1, view(P, T.out[1]), none, 0, 0, P + T.out[1].b, T.bf16, s);
   // transposed: element (k, n) of W^T is W[n][k]
-  fill(T.ne2T, H, H, view(P, T.ne[1], 0, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.ee2T, H, H, view(P, T.ee[1], 0, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.ecT, H, H, view(P, T.en[0], 2 * H, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.eabT, 2 * H, H, view(P, T.en[0], 0, 1), view(P, T.en[0], H, 1), 2, H, nullptr, 0, s);
-  fill(T.e2T, H, H, view(P, T.en[1], 0, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.n1T, H, 2 * H, view(P, T.nn[0], 0, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.n2T, H, H, view(P, T.nn[1], 0, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.ocT, H, H, view(P, T.out[0], 2 * H, 1), none, 0, 0, nullptr, 0, s);
-  fill(T.oabT, 2 * H, H, view(P, T.out[0], 0, 1), view(P, T.out[0], H, 1), 2, H, nullptr, 0, s);
-  // the context's inference layers (FP32 context): same blocks as the forward ones
+  fill(T.ne2T, H, H, view(P, T.ne[1], 0, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.ee2T, H, H, view(P, T.ee[1], 0, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.ecT, H, H, view(P, T.en[0], 2 * H, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.eabT, 2 * H, H, view(P, T.en[0], 0, 1), view(P, T.en[0], H, 1), 2, H, nullptr, T.bf16, s);
+  fill(T.e2T, H, H, view(P, T.en[1], 0, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.n1T, H, 2 * H, view(P, T.nn[0], 0, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.n2T, H, H, view(P, T.nn[1], 0, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.ocT, H, H, view(P, T.out[0], 2 * H, 1), none, 0, 0, nullptr, T.bf16, s);
+  fill(T.oabT, 2 * H, H, view(P, T.out[0], 0, 1), view(P, T.out[0], H, 1), 2, H, nullptr, T.bf16, s);
+  // the context's inference layers, in the context's precision
+  const int inf_bf16 = c->prec == TRK_PREC_BF16 ? 1 : 0;
   auto same = [&](DevLayer& dst, const LayerOff& o, int r0, int K, MatView B = MatView(), int mode = 0) {
-    fill(dst, K, o.N * (mode == 1 ? 2 : 1), view(P, o, r0), B, mode, o.N, mode == 1 ? nullptr : P + o.b, 0, s);
+    fill(dst, K, o.N * (mode == 1 ? 2 : 1), view(P, o, r0), B, mode, o.N, mode == 1 ? nullptr : P + o.b, inf_bf16,
+         s);
   };
   for (int i = 0; i <= c->cfg.emb_layers; ++i) {
     const LayerOff& o = T.emb[i];
-    fill(T.embF[i], o.K, o.N, view(P, o), none, 0, 0, P + o.b, 0, s);
-    if (i >= 1) fill(T.embT[i], o.N, o.K, view(P, o, 0, 1), none, 0, 0, nullptr, 0, s);
+    fill(T.embF[i], o.K, o.N, view(P, o), none, 0, 0, P + o.b, T.bf16, s);
+    if (i >= 1) fill(T.embT[i], o.N, o.K, view(P, o, 0, 1), none, 0, 0, nullptr, T.bf16, s);
   }
   same(c->emb_in, T.emb[0], 0, 3);
   for (int i = 1; i < c->cfg.emb_layers; ++i) same(c->emb_hid.l[i - 1], T.emb[i], 0, T.emb[i].K);
@@ -768,12 +863,12 @@ int trk_filter_train_fwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
   int lda = 2 * D, K = 2 * D;
   for (int i = 0; i < L; ++i) {
     float* o = T.fact + (size_t)i * T.cap_c * F;
-    rowgemm(a, lda, K, m, T.filtF[i], o, F, F, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(a, lda, K, m, T.filtF[i], o, F, F, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     a = o;
     lda = F;
     K = F;
   }
-  rowgemm(a, F, F, m, T.filtF[L], d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s);
+  rowgemm(a, F, F, m, T.filtF[L], d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s, T.bf16);
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
 }
 
@@ -796,7 +891,7 @@ int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
       wgrad(T, T.fact + (size_t)(i - 1) * T.cap_c * F, F, nullptr, nullptr, nullptr, 0, 0, F, true, del, F, F, m,
             d_grads + T.filt[i].w, s);
     if (i >= 1) {
-      rowgemm(del, F, F, m, T.filtT[i], nxt, F, F, EPI_DTANH, T.fact + (size_t)(i - 1) * T.cap_c * F, F, c->n_cu, s);
+      rowgemm(del, F, F, m, T.filtT[i], nxt, F, F, EPI_DTANH, T.fact + (size_t)(i - 1) * T.cap_c * F, F, c->n_cu, s, T.bf16);
       std::swap(del, nxt);
     }
   }
@@ -812,34 +907,34 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   const int H = c->cfg.gnn_hidden, It = c->cfg.gnn_iters;
   const int nn = (int)n;
   launch_incidence(d_src, d_dst, m, nullptr, nn, g, s);
-  rowgemm(d_x, 3, 3, n, T.ne1, T.na1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
-  rowgemm(T.na1, H, H, n, T.ne2, T.hck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+  rowgemm(d_x, 3, 3, n, T.ne1, T.na1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
+  rowgemm(T.na1, H, H, n, T.ne2, T.hck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
   ew(pair_gather_kernel, m * 6, s, d_x, 3, nn, d_src, d_dst, m, T.x6, 6);
-  rowgemm(T.x6, 6, 6, m, T.ee1, T.ea1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
-  rowgemm(T.ea1, H, H, m, T.ee2, T.eck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+  rowgemm(T.x6, 6, 6, m, T.ee1, T.ea1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
+  rowgemm(T.ea1, H, H, m, T.ee2, T.eck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
   for (int t = 1; t <= It; ++t) {
     const float* h = T.hck + (size_t)(t - 1) * T.nmax * H;
     const float* e = T.eck + (size_t)(t - 1) * T.cap_f * H;
     float* h_new = T.hck + (size_t)t * T.nmax * H;
     float* e_new = T.eck + (size_t)t * T.cap_f * H;
-    rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
-    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
+    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
-    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     ew(add_kernel, m * H, s, e, T.v, e_new, m * H);
     segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
     ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
-    rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
-    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
+    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     ew(add_kernel, n * H, s, h, T.q2, h_new, n * H);
   }
   const float* hT = T.hck + (size_t)It * T.nmax * H;
   const float* eT = T.eck + (size_t)It * T.cap_f * H;
-  rowgemm(hT, H, H, n, T.oab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
+  rowgemm(hT, H, H, n, T.oab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
   if (m > 0) {
-    rowgemm(eT, H, H, m, T.oc, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    rowgemm(eT, H, H, m, T.oc, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.oc.b, d_src, d_dst, nn, m, H, T.u);
-    rowgemm(T.u, H, H, m, T.o2, d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s);
+    rowgemm(T.u, H, H, m, T.o2, d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s, T.bf16);
   }
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
 }
@@ -867,53 +962,53 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   wgrad(T, eT, H, nullptr, nullptr, nullptr, 0, 0, H, true, du, H, H, m, G + T.out[0].w + (size_t)2 * H * H, s);
   float* dh = T.dh;
   float* dh2 = T.dh2;
-  rowgemm(T.dP, 2 * H, 2 * H, n, T.oabT, dh, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
-  rowgemm(du, H, H, m, T.ocT, T.de, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+  rowgemm(T.dP, 2 * H, 2 * H, n, T.oabT, dh, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
+  rowgemm(du, H, H, m, T.ocT, T.de, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
   for (int t = It; t >= 1; --t) {
     const float* h = T.hck + (size_t)(t - 1) * T.nmax * H;
     const float* e = T.eck + (size_t)(t - 1) * T.cap_f * H;
     const float* e_new = T.eck + (size_t)t * T.cap_f * H;
     // recompute this iteration's internals from (h^{t-1}, e^{t-1})
-    rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
-    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
+    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
-    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
     ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
-    rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
-    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
+    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     // node update h^t = h + phi_v([h, msg])
     ew(dtanh_kernel, n * H, s, dh, T.q2, n * H, T.dq);
     wgrad(T, T.q1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dq, H, H, n, G + T.nn[1].w, s);
-    rowgemm(T.dq, H, H, n, T.n2T, T.dq1, H, H, EPI_DTANH, T.q1, H, c->n_cu, s);
+    rowgemm(T.dq, H, H, n, T.n2T, T.dq1, H, H, EPI_DTANH, T.q1, H, c->n_cu, s, T.bf16);
     wgrad(T, T.nin, 2 * H, nullptr, nullptr, nullptr, 0, 0, 2 * H, true, T.dq1, H, H, n, G + T.nn[0].w, s);
-    rowgemm(T.dq1, H, H, n, T.n1T, T.dnin, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s);
+    rowgemm(T.dq1, H, H, n, T.n1T, T.dnin, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     ew(add_cols_kernel, n * H, s, dh, T.dnin, 2 * H, n, H, dh2);
     // messages: de^t += dmsg[src] + dmsg[dst]
     if (m > 0) ew(gather_add_kernel, m * H, s, T.dnin + H, 2 * H, d_src, d_dst, nn, m, H, T.de);
     // edge update e^t = e + phi_e([h_s, h_t, e])
     ew(dtanh_kernel, m * H, s, T.de, T.v, m * H, T.dpre);
     wgrad(T, T.t1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dpre, H, H, m, G + T.en[1].w, s);
-    rowgemm(T.dpre, H, H, m, T.e2T, T.dpre1, H, H, EPI_DTANH, T.t1, H, c->n_cu, s);
+    rowgemm(T.dpre, H, H, m, T.e2T, T.dpre1, H, H, EPI_DTANH, T.t1, H, c->n_cu, s, T.bf16);
     wgrad(T, e, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dpre1, H, H, m, G + T.en[0].w + (size_t)2 * H * H, s);
     segsum(T.dpre1, H, g.rowptr, g.rowidx, nullptr, nullptr, nn, T.dP, 2 * H, s);
     segsum(T.dpre1, H, g.cscptr, g.cscidx, nullptr, nullptr, nn, T.dP + H, 2 * H, s);
     wgrad(T, h, H, nullptr, nullptr, nullptr, 0, 0, H, false, T.dP, 2 * H, H, n, G + T.en[0].w, s);
     wgrad(T, h, H, nullptr, nullptr, nullptr, 0, 0, H, false, T.dP + H, 2 * H, H, n, G + T.en[0].w + (size_t)H * H, s);
-    rowgemm(T.dpre1, H, H, m, T.ecT, T.de, H, H, EPI_ACC, nullptr, 0, c->n_cu, s);
-    rowgemm(T.dP, 2 * H, 2 * H, n, T.eabT, dh2, H, H, EPI_ACC, nullptr, 0, c->n_cu, s);
+    rowgemm(T.dpre1, H, H, m, T.ecT, T.de, H, H, EPI_ACC, nullptr, 0, c->n_cu, s, T.bf16);
+    rowgemm(T.dP, 2 * H, 2 * H, n, T.eabT, dh2, H, H, EPI_ACC, nullptr, 0, c->n_cu, s, T.bf16);
     std::swap(dh, dh2);
   }
   // encoders
   if (m > 0) {
     ew(dtanh_kernel, m * H, s, T.de, T.eck, m * H, T.dpre);
     wgrad(T, T.ea1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dpre, H, H, m, G + T.ee[1].w, s);
-    rowgemm(T.dpre, H, H, m, T.ee2T, T.dpre1, H, H, EPI_DTANH, T.ea1, H, c->n_cu, s);
+    rowgemm(T.dpre, H, H, m, T.ee2T, T.dpre1, H, H, EPI_DTANH, T.ea1, H, c->n_cu, s, T.bf16);
     wgrad(T, T.x6, 6, nullptr, nullptr, nullptr, 0, 0, 6, true, T.dpre1, H, H, m, G + T.ee[0].w, s);
   }
   ew(dtanh_kernel, n * H, s, dh, T.hck, n * H, T.dq);
   wgrad(T, T.na1, H, nullptr, nullptr, nullptr, 0, 0, H, true, T.dq, H, H, n, G + T.ne[1].w, s);
-  rowgemm(T.dq, H, H, n, T.ne2T, T.dq1, H, H, EPI_DTANH, T.na1, H, c->n_cu, s);
+  rowgemm(T.dq, H, H, n, T.ne2T, T.dq1, H, H, EPI_DTANH, T.na1, H, c->n_cu, s, T.bf16);
   wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 0, 3, true, T.dq1, H, H, n, G + T.ne[0].w, s);
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
 }
@@ -927,12 +1022,12 @@ int trk_embed_train_fwd(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, h
   int lda = 3, K = 3;
   for (int i = 0; i < EL; ++i) {
     float* o = T.eact + (size_t)i * T.nmax * EW;
-    rowgemm(a, lda, K, n, T.embF[i], o, EW, EW, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s);
+    rowgemm(a, lda, K, n, T.embF[i], o, EW, EW, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     a = o;
     lda = EW;
     K = EW;
   }
-  rowgemm(a, EW, EW, n, T.embF[EL], d_emb, D, D, EPI_BIAS, nullptr, 0, c->n_cu, s);
+  rowgemm(a, EW, EW, n, T.embF[EL], d_emb, D, D, EPI_BIAS, nullptr, 0, c->n_cu, s, T.bf16);
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
 }
 
@@ -946,14 +1041,14 @@ int trk_embed_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const float* d_
   wgrad(T, act(EL), EW, nullptr, nullptr, nullptr, 0, 0, EW, true, d_demb, D, D, n, d_grads + T.emb[EL].w, s);
   float* del = T.edel0;
   float* nxt = T.edel1;
-  rowgemm(d_demb, D, D, n, T.embT[EL], del, EW, EW, EPI_DTANH, act(EL), EW, c->n_cu, s);
+  rowgemm(d_demb, D, D, n, T.embT[EL], del, EW, EW, EPI_DTANH, act(EL), EW, c->n_cu, s, T.bf16);
   for (int i = EL - 1; i >= 0; --i) {
     if (i == 0)
       wgrad(T, d_x, 3, nullptr, nullptr, nullptr, 0, 0, 3, true, del, EW, EW, n, d_grads + T.emb[0].w, s);
     else
       wgrad(T, act(i), EW, nullptr, nullptr, nullptr, 0, 0, EW, true, del, EW, EW, n, d_grads + T.emb[i].w, s);
     if (i >= 1) {
-      rowgemm(del, EW, EW, n, T.embT[i], nxt, EW, EW, EPI_DTANH, act(i), EW, c->n_cu, s);
+      rowgemm(del, EW, EW, n, T.embT[i], nxt, EW, EW, EPI_DTANH, act(i), EW, c->n_cu, s, T.bf16);
       std::swap(del, nxt);
     }
   }

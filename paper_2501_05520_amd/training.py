@@ -9,12 +9,18 @@ from . import trk
 
 
 class TrainContext:
-    """An FP32 context with training buffers and a flat FP32 parameter vector."""
+    """A context with training buffers and a flat FP32 parameter vector.
+    precision "fp32": FP32 products; "bf16": every product with BF16 operands and
+    FP32 accumulation (FP32 master parameters, moments and stored activations)."""
 
-    def __init__(self, cfg, nets, device=0, max_hits=None, max_cand_edges=None, max_kept_edges=None):
+    def __init__(self, cfg, nets, device=0, max_hits=None, max_cand_edges=None, max_kept_edges=None,
+                 precision="fp32"):
+        if precision not in ("fp32", "bf16"):
+            raise ValueError("training runs in fp32 or bf16")
         self.cfg = cfg
+        self.precision = precision
         self.device = torch.device("cuda", device)
-        self.config = trk.make_config(cfg, "fp32", max_hits, max_cand_edges, max_kept_edges, 1, False, True)
+        self.config = trk.make_config(cfg, precision, max_hits, max_cand_edges, max_kept_edges, 1, False, True)
         self.ctx = trk.trk_create(self.config, trk.pack_weights(cfg, nets), device)
         self.n_params = trk.trk_train_param_count(self.config)
         flat = trk.flatten_params(nets)

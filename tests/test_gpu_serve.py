@@ -46,15 +46,16 @@ def test_tiny_mix_equals_alone():
     assert st["completed"] == len(xs) and st["batches"] < len(xs)
 
 
-def test_mu_mix_bf16_equals_alone():
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+def test_mu_mix_equals_alone(precision):
     from paper_2501_05520_amd.trk import Server, Pipeline
     nets = make_weights(MU200, 0)
     xs = [generate_event(400 + k, mu).x for k, mu in enumerate((50, 100, 140, 50, 100, 140))]
-    srv = Server(MU200, nets, "bf16", n_slots=2, max_batch_events=4, max_batch_hits=160000)
+    srv = Server(MU200, nets, precision, n_slots=2, max_batch_events=4, max_batch_hits=160000)
     res = _serve_many(srv, xs, 6)
     st = srv.stats()
     srv.close()
-    pipe = Pipeline(MU200, nets, "bf16", max_hits=80000)
+    pipe = Pipeline(MU200, nets, precision, max_hits=80000)
     for x, (rc, labels, info, lat) in zip(xs, res):
         assert rc == 0
         alone, _ = pipe.event(x)

@@ -229,3 +229,83 @@ def test_embedding_training_gradient(full_width):
     trk.trk_embed(tc.ctx, x, e2)
     assert torch.allclose(e2, emb, rtol=0, atol=1e-5 * max(1.0, float(emb.abs().max())))
     tc.close()
+
+
+# ---------------------------------------------------------------- BF16 products
+# Each BF16 operand is within 2^-9 of its FP32 value; a gradient passes through
+# about a dozen products (forward and backward), so its norm-wise error against the
+# FP64 oracle is a few times 2^-9 x sqrt(depth) ~ 1e-2; the bound leaves a factor 3.
+GRAD_RTOL_BF16 = 3e-2
+
+
+@pytest.fixture(scope="module")
+def setup_bf16():
+    from paper_2501_05520_amd.training import TrainContext
+    cfg = TINY.with_(gnn_iters=2)
+    nets = make_weights(cfg, 0)
+    ev = generate_event(3, 1)
+    r = oracle.event(ev.x, nets, cfg)
+    tc = TrainContext(cfg, nets, max_hits=4096, max_cand_edges=60000, max_kept_edges=60000, precision="bf16")
+    yield cfg, nets, ev, r, tc
+    tc.close()
+
+
+def test_bf16_training_gradients(setup_bf16):
+    """Training context in BF16 (BF16 operands, FP32 accumulation, FP32 master
+    parameters): logits and every per-tensor gradient of the filter and of the
+    interaction network against the FP64 oracle."""
+    from paper_2501_05520_amd import trk
+    cfg, nets, ev, r, tc = setup_bf16
+    emb = r["emb"].astype(np.float32)
+    yc = OT.edge_truth(ev.pid, r["src"], r["dst"])
+    _, zc, gc = OT.filter_loss_and_grad(emb, r["src"], r["dst"], yc, nets)
+    demb, ds, dd = _dev(emb, torch.float32), _dev(r["src"], torch.int32), _dev(r["dst"], torch.int32)
+    logits = torch.empty(ds.numel(), device="cuda")
+    trk.trk_filter_train_fwd(tc.ctx, demb, ds, dd, logits)
+    dz = torch.empty_like(logits)
+    trk.trk_bce_with_logits(tc.ctx, logits, _dev(yc, torch.float32), dz)
+    g = torch.zeros(tc.n_params, device="cuda")
+    trk.trk_filter_train_bwd(tc.ctx, demb, ds, dd, dz, g)
+    ez = np.max(np.abs(logits.cpu().numpy() - zc) / np.maximum(1.0, np.abs(zc)))
+    gn = _split(g.cpu().numpy(), nets)
+    errs = {("filt", li, "W"): _rel(gn["filt"][li][0], gw) for li, (gw, gb) in enumerate(gc)}
+    yf = OT.edge_truth(ev.pid, r["fsrc"], r["fdst"])
+    _, zg, gg = OT.gnn_loss_and_grad(ev.x, r["fsrc"], r["fdst"], yf, nets, cfg.gnn_iters)
+    dx, fs, fd = _dev(ev.x, torch.float32), _dev(r["fsrc"], torch.int32), _dev(r["fdst"], torch.int32)
+    lg = torch.empty(fs.numel(), device="cuda")
+    trk.trk_gnn_train_fwd(tc.ctx, dx, fs, fd, lg)
+    dzg = torch.empty_like(lg)
+    trk.trk_bce_with_logits(tc.ctx, lg, _dev(yf, torch.float32), dzg)
+    g2 = torch.zeros(tc.n_params, device="cuda")
+    trk.trk_gnn_train_bwd(tc.ctx, dx, fs, fd, dzg, g2)
+    ezg = np.max(np.abs(lg.cpu().numpy() - zg) / np.maximum(1.0, np.abs(zg)))
+    gn2 = _split(g2.cpu().numpy(), nets)
+    for name in ("out", "node_net", "edge_net", "edge_enc", "node_enc"):
+        for li, (gw, gb) in enumerate(gg[name]):
+            errs[(name, li, "W")] = _rel(gn2[name][li][0], gw)
+            errs[(name, li, "b")] = _rel(gn2[name][li][1], gb)
+    worst = max(errs.items(), key=lambda kv: kv[1])
+    print(f"bf16 training: filter logits {ez:.3g}, gnn logits {ezg:.3g}; worst gradient {worst}")
+    # logits (relative to max(1, |z|)): the interaction network's pass through its
+    # encoders, T iterations and the output head chains about ten BF16 products; 5e-2
+    # was seen at T = 2, the bound leaves a factor 3
+    assert ez <= 0.15 and ezg <= 0.15
+    assert worst[1] <= GRAD_RTOL_BF16, worst
+
+
+def test_bf16_training_lowers_the_loss():
+    from paper_2501_05520_amd.training import TrainContext, train_step, edge_truth
+    cfg = TINY
+    nets = make_weights(cfg, 0)
+    ev = generate_event(7, 1)
+    r = oracle.event(ev.x, nets, cfg)
+    tc = TrainContext(cfg, nets, max_hits=4096, max_cand_edges=60000, max_kept_edges=60000, precision="bf16")
+    x = _dev(ev.x, torch.float32)
+    emb = _dev(r["emb"].astype(np.float32), torch.float32)
+    cand = (_dev(r["src"], torch.int32), _dev(r["dst"], torch.int32))
+    filt = (_dev(r["fsrc"], torch.int32), _dev(r["fdst"], torch.int32))
+    yc = _dev(edge_truth(ev.pid, r["src"], r["dst"]), torch.float32)
+    yf = _dev(edge_truth(ev.pid, r["fsrc"], r["fdst"]), torch.float32)
+    losses = [sum(train_step(tc, x, emb, cand, filt, yc, yf, lr=3e-3)) for _ in range(30)]
+    tc.close()
+    assert losses[-1] < 0.8 * losses[0], losses
