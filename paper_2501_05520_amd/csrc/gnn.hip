@@ -16,6 +16,7 @@
 #include "kernels.h"
 #include "mfma_tile.h"
 #include <algorithm>
+#include <type_traits>
 #include <stdlib.h>
 
 namespace {
@@ -618,20 +619,26 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
                                                                net.edge_2, net.out_2, scores);
 }
 
-// Row tiles of the H=128 kernels (edge tile, node tile): smaller tiles use less LDS and
-// let more workgroups share a CU.
+// Row tiles of the H=128 kernels (edge tile, node tile, waves): smaller tiles use less
+// LDS and let more workgroups share a CU; eight-wave workgroups on 64 edges halve the
+// weight reads per edge.  Measured defaults: 64 edges with eight waves for FP32 and
+// BF16, 32 edges with four waves for split BF16 (whose 4-byte tiles would leave one
+// workgroup per CU).  TRK_GNN_TILE overrides.
+template <class P>
 int gnn_tile_variant() {
   const char* e = getenv("TRK_GNN_TILE");
-  return e ? atoi(e) : 2;
+  return e ? atoi(e) : std::is_same<P, PrecX3>::value ? 2 : 6;
 }
 
 template <class P>
 void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
                 const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool sorted) {
-  switch (gnn_tile_variant()) {
+  switch (gnn_tile_variant<P>()) {
     case 0: run_gnn<P, 128, 64, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     case 2: run_gnn<P, 128, 32, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     case 3: run_gnn<P, 128, 32, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    case 5: run_gnn<P, 128, 64, 32, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    case 6: run_gnn<P, 128, 64, 64, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
   }
 }
