@@ -57,8 +57,11 @@ __global__ void uf_init_min(int* parent, const int* __restrict__ src, const int*
   GRID_STRIDE(e, m) {
     if (!scores || scores[e] > cut) {
       const int a = src[e], b = dst[e];
-      if ((unsigned)a < (unsigned)n && (unsigned)b < (unsigned)n && a != b)
-        atomicMin(&parent[a > b ? a : b], a > b ? b : a);
+      if ((unsigned)a < (unsigned)n && (unsigned)b < (unsigned)n && a != b) {
+        const int hi = a > b ? a : b, lo = a > b ? b : a;
+        // a parent only decreases, so a (possibly stale) value <= lo makes the atomic moot
+        if (parent[hi] > lo) atomicMin(&parent[hi], lo);
+      }
     }
   }
 }
@@ -104,7 +107,9 @@ __global__ void uf_hook_min(int* parent, const int* __restrict__ src, const int*
     }
     const int t_next = __shfl_down(tgt, 1, 64);
     const bool last = l == 63 || t_next != tgt;
-    if (tgt >= 0 && last) atomicMin(&parent[tgt], val);
+    // skip the atomic when the target already points at val or lower (parents only
+    // decrease, so a stale read errs on the side of issuing it)
+    if (tgt >= 0 && last && parent[tgt] > val) atomicMin(&parent[tgt], val);
   }
 }
 
