@@ -85,7 +85,8 @@ __global__ __launch_bounds__(STAT_T) void stats_kernel(const float* __restrict__
 }
 
 // One block: sum partials (fixed order), form the covariance, run subspace
-// iteration for the three leading eigenvectors and orthonormalise them (FP64).
+// iteration for the three leading eigenvectors on its fourth power and
+// orthonormalise them (FP64).
 // basis layout (doubles): [0..3*EP) directions, then cell edge, then spare.
 __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ part, int nblocks, int n, int D,
                                                     float radius, double* __restrict__ basis) {
@@ -112,6 +113,25 @@ __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ p
     C[a][b] = v;
   }
   __syncthreads();
+  // iterate with the fourth power of the trace-normalised covariance (same
+  // eigenvectors, eigenvalue ratios to the fourth power: one step does the work of
+  // four); its eigenvalues lie in [0, 1]
+  __shared__ double C2[EP][EP];
+  {
+    double tr = 0.0;
+    for (int q = 0; q < EP; ++q) tr += C[q][q];
+    const double inv = tr > 0.0 ? 1.0 / tr : 1.0;
+    const int a = t / EP, b = t % EP;
+    double v = 0.0;
+    for (int q = 0; q < EP; ++q) v += C[a][q] * C[q][b];
+    __syncthreads();
+    C2[a][b] = v * inv * inv;
+    __syncthreads();
+    v = 0.0;
+    for (int q = 0; q < EP; ++q) v += C2[a][q] * C2[q][b];
+    C[a][b] = v;
+  }
+  __syncthreads();
   // the iteration runs in one wave, in registers: lane l < 3 EP holds V[l / EP][l % EP]
   if (t >= 64) return;
   const int l = t, c = l / EP, k = l % EP;
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ p
   };
   // fixed dense start, distinct per column
   double v = (l < 3 * EP && k < D) ? cos(0.7 * (k + 1) * (c + 1) + 0.3 * c) : 0.0;
-  for (int it = 0; it < 24; ++it) {
+  for (int it = 0; it < 8; ++it) {
     double w = 0.0;
     for (int q = 0; q < EP; ++q) w += C[k][q] * __shfl(v, (c < 3 ? c : 3) * EP + q, 64);
     // keep a small multiple of the start vector so rank-deficient covariances still
