@@ -196,16 +196,18 @@ __global__ void cell_kernel(const float* __restrict__ emb, int n, int D, const i
   }
 }
 
-__global__ void scatter_kernel(const float* __restrict__ emb, int n, int D, const unsigned long long* __restrict__ cell,
-                               const int* __restrict__ bucket, const int* __restrict__ start, int* __restrict__ fill,
-                               int* __restrict__ sorted_id, float* __restrict__ sorted_emb,
-                               unsigned long long* __restrict__ sorted_cell) {
+// sorted_emb rows hold es = 4 ceil(D / 4) floats (12 for D = 12): the query passes
+// read every candidate's row, so rows carry no padding beyond the last float4
+__global__ void scatter_kernel(const float* __restrict__ emb, int n, int D, int es,
+                               const unsigned long long* __restrict__ cell, const int* __restrict__ bucket,
+                               const int* __restrict__ start, int* __restrict__ fill, int* __restrict__ sorted_id,
+                               float* __restrict__ sorted_emb, unsigned long long* __restrict__ sorted_cell) {
   GRID_STRIDE(i, n) {
     const int b = bucket[i];
     const int pos = start[b] + atomicAdd(&fill[b], 1);
     sorted_id[pos] = (int)i;
     sorted_cell[pos] = cell[i];
-    for (int k = 0; k < EP; ++k) sorted_emb[(size_t)pos * EP + k] = (k < D) ? emb[i * D + k] : 0.f;
+    for (int k = 0; k < es; ++k) sorted_emb[(size_t)pos * es + k] = (k < D) ? emb[i * D + k] : 0.f;
   }
 }
 
@@ -215,10 +217,11 @@ __global__ void scatter_kernel(const float* __restrict__ emb, int n, int D, cons
 struct QueryCtx {
   const int* start;
   const int* sorted_id;
-  const float* sorted_emb;
+  const float* sorted_emb;   // [n][es]: the D coordinates, zero-padded to a multiple of 4
   const unsigned long long* sorted_cell;
   int64_t tmask;
   float r2;
+  int nk4;                   // float4 chunks per point (es = 4 nk4 <= EP)
 };
 
 struct WaveSlots {
@@ -270,10 +273,10 @@ __device__ __forceinline__ void for_neighbours(const QueryCtx& qc, WaveSlots& ws
       const int entry = ws.bstart[lo] + (fidx - ws.pre[lo]);
       const unsigned long long ck = qc.sorted_cell[entry];
       const int jj = qc.sorted_id[entry];
-      const float4* pe = (const float4*)(qc.sorted_emb + (size_t)entry * EP);
+      const float4* pe = (const float4*)(qc.sorted_emb + (size_t)entry * 4 * qc.nk4);
       float4 v[EP / 4];
 #pragma unroll
-      for (int k4 = 0; k4 < EP / 4; ++k4) v[k4] = pe[k4];
+      for (int k4 = 0; k4 < EP / 4; ++k4) v[k4] = k4 < qc.nk4 ? pe[k4] : make_float4(0.f, 0.f, 0.f, 0.f);
       if (ck == ws.key[lo]) {
         j = jj;
         if (j != i) {
@@ -311,10 +314,10 @@ __device__ __forceinline__ void load_query(const QueryCtx& qc, int64_t q, int& i
                                            float (&qe)[EP]) {
   i = qc.sorted_id[q];
   qcell = qc.sorted_cell[q];
-  const float4* pe = (const float4*)(qc.sorted_emb + (size_t)q * EP);
+  const float4* pe = (const float4*)(qc.sorted_emb + (size_t)q * 4 * qc.nk4);
 #pragma unroll
   for (int k4 = 0; k4 < EP / 4; ++k4) {
-    const float4 v = pe[k4];
+    const float4 v = k4 < qc.nk4 ? pe[k4] : make_float4(0.f, 0.f, 0.f, 0.f);
     qe[4 * k4] = v.x; qe[4 * k4 + 1] = v.y; qe[4 * k4 + 2] = v.z; qe[4 * k4 + 3] = v.w;
   }
 }
@@ -523,9 +526,10 @@ void launch_build_graph(const float* emb, int n, int D, float radius, int k_max,
   const int eb = blocks_for(n, 256);
   cell_kernel<<<eb, 256, 0, s>>>(emb, n, D, ev, g.basis, g.table - 1, g.cell, g.bucket, g.hist);
   launch_scan_excl(g.hist, g.start, g.table, nullptr, nullptr, g.tmp, s);
-  scatter_kernel<<<eb, 256, 0, s>>>(emb, n, D, g.cell, g.bucket, g.start, g.fill, g.sorted_id, g.sorted_emb,
+  const int nk4 = (D + 3) / 4;
+  scatter_kernel<<<eb, 256, 0, s>>>(emb, n, D, 4 * nk4, g.cell, g.bucket, g.start, g.fill, g.sorted_id, g.sorted_emb,
                                     g.sorted_cell);
-  QueryCtx qc{g.start, g.sorted_id, g.sorted_emb, g.sorted_cell, g.table - 1, radius * radius};
+  QueryCtx qc{g.start, g.sorted_id, g.sorted_emb, g.sorted_cell, g.table - 1, radius * radius, nk4};
   int qgrid = (int)((n + QW - 1) / QW);
   if (qgrid > n_cu * 16) qgrid = n_cu * 16;
   qgrid = ((qgrid + 7) / 8) * 8;
