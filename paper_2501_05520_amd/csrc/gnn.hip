@@ -414,7 +414,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
       const int k0 = base + l;
       const int my = l < cnt ? (k0 < cs ? sidx[bs + k0] : didx[bd + k0 - cs]) : 0;
       const int steps = (cnt + RPS - 1) / RPS;   // uniform over the wave: the shuffle needs every lane
-#pragma unroll 4
+#pragma unroll 8
       for (int st = 0; st < steps; ++st) {
         const int k = grp + st * RPS;
         const int eid = __shfl(my, k < cnt ? k : 0, 64);
