@@ -229,8 +229,9 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
 // The gathered projections are summed into an FP32 LDS tile with coalesced row
 // loads before the product; the hidden activation t1 reuses that tile.
 // ---------------------------------------------------------------------------
-template <class P, int H, int MT, int NW, bool OUT>
-__global__ __launch_bounds__(NW * 64) void edge_kernel(typename P::act_t* __restrict__ e,
+// WPE: waves per SIMD the registers must allow (default: one workgroup's worth)
+template <class P, int H, int MT, int NW, bool OUT, int WPE = NW / 4>
+__global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* __restrict__ e,
                                                        const typename P::act_t* __restrict__ proj,
                                                        const int* __restrict__ src, const int* __restrict__ dst,
                                                        int n, int64_t m_cap, const int* d_m, DevLayer lc, DevLayer l2,
@@ -589,7 +590,7 @@ bool gnn_shapes_ok(const DevGNN& net) {
   return net.H == H && net.node_enc1.nkb == nkb(3) && net.edge_enc1.nkb == nkb(6) && net.node_1.nkb == nkb(2 * H);
 }
 
-template <class P, int H, int MTE, int MTN, int NW>
+template <class P, int H, int MTE, int MTN, int NW, int EWPE = NW / 4>
 void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap, const int* d_m,
              float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool src_sorted) {
   typedef typename P::act_t T;
@@ -607,7 +608,7 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
                                                                 net.edge_enc2, e, d_err);
   for (int it = 0; it < net.iters; ++it) {
     if (egrid > 0)
-      edge_kernel<P, H, MTE, NW, false><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
+      edge_kernel<P, H, MTE, NW, false, EWPE><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
                                                                   net.edge_2, net.out_2, nullptr);
     const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
     aggregate_kernel<P, H><<<agg_blocks(n, n_cu), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
@@ -615,19 +616,20 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
       node_step_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
   }
   if (egrid > 0)
-    edge_kernel<P, H, MTE, NW, true><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,
+    edge_kernel<P, H, MTE, NW, true, EWPE><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,
                                                                net.edge_2, net.out_2, scores);
 }
 
 // Row tiles of the H=128 kernels (edge tile, node tile, waves): smaller tiles use less
 // LDS and let more workgroups share a CU; eight-wave workgroups on 64 edges halve the
-// weight reads per edge.  Measured defaults: 64 edges with eight waves for FP32 and
-// BF16, 32 edges with four waves for split BF16 (whose 4-byte tiles would leave one
-// workgroup per CU).  TRK_GNN_TILE overrides.
+// weight reads per edge.  The default (8) is 64 edges on eight waves with the edge
+// kernel's registers held to four waves per SIMD, so that two workgroups share a CU
+// in every precision (measured best, or level with variant 6, in FP32, BF16 and split
+// BF16).  TRK_GNN_TILE overrides.
 template <class P>
 int gnn_tile_variant() {
   const char* e = getenv("TRK_GNN_TILE");
-  return e ? atoi(e) : std::is_same<P, PrecX3>::value ? 2 : 6;
+  return e ? atoi(e) : 8;
 }
 
 template <class P>
@@ -639,6 +641,7 @@ void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const 
     case 3: run_gnn<P, 128, 32, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     case 5: run_gnn<P, 128, 64, 32, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     case 6: run_gnn<P, 128, 64, 64, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    case 8: run_gnn<P, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
   }
 }
