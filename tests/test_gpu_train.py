@@ -309,3 +309,33 @@ def test_bf16_training_lowers_the_loss():
     losses = [sum(train_step(tc, x, emb, cand, filt, yc, yf, lr=3e-3)) for _ in range(30)]
     tc.close()
     assert losses[-1] < 0.8 * losses[0], losses
+
+
+def test_bf16_embedding_training_gradient():
+    """Embedding training in a BF16 context (tiny widths): forward and gradients
+    against the FP64 oracle, to the BF16 bound."""
+    from paper_2501_05520_amd import trk
+    from paper_2501_05520_amd.training import TrainContext
+    cfg = TINY
+    nets = make_weights(cfg, 0)
+    ev = generate_event(6, 2)
+    pa, pb, y = _pairs(ev, np.random.default_rng(2))
+    margin, lam = float(cfg.radius), 10.0
+    _, emb_ref, grads = OT.embed_loss_and_grad(ev.x, pa, pb, y, margin, nets, neg_weight=lam)
+    tc = TrainContext(cfg, nets, max_hits=4096, max_cand_edges=20000, max_kept_edges=1000, precision="bf16")
+    x = _dev(ev.x, torch.float32)
+    emb = torch.empty((ev.n, cfg.emb_dim), device="cuda")
+    trk.trk_embed_train_fwd(tc.ctx, x, emb)
+    ee = np.max(np.abs(emb.cpu().numpy() - emb_ref) / np.maximum(1.0, np.abs(emb_ref)))
+    demb = torch.empty_like(emb)
+    trk.trk_pair_loss(tc.ctx, emb, _dev(pa, torch.int32), _dev(pb, torch.int32), _dev(y, torch.float32), margin,
+                      demb, neg_weight=lam)
+    g = torch.zeros(tc.n_params, device="cuda")
+    trk.trk_embed_train_bwd(tc.ctx, x, demb, g)
+    tc.close()
+    gn = _split(g.cpu().numpy(), nets)
+    errs = [_rel(gn["emb"][li][0], gw) for li, (gw, _) in enumerate(grads)]
+    print(f"bf16 embedding training: forward {ee:.3g}, weight gradients {[round(v, 4) for v in errs]}")
+    # the pair gradient is taken at the BF16 forward's own embedding, whose error adds
+    # to that of the backward products: twice the per-network bound
+    assert ee <= 0.05 and max(errs) <= 2 * GRAD_RTOL_BF16
