@@ -353,6 +353,21 @@ def train_measure(cfg, nets, steps, torch, trk, precision="fp32"):
                                   "and stored states"}[precision]}
 
 
+def measured_peaks(torch, trk):
+    """Dense MFMA rate of each precision from independent MFMA chains on every CU,
+    and the HBM bandwidth of a 1 GiB device-to-device copy (read + write)."""
+    out = {"fp32_mfma_tflops": round(trk.trk_probe_mfma("fp32", 100_000), 1),
+           "bf16_mfma_tflops": round(trk.trk_probe_mfma("bf16", 200_000), 1),
+           "fp8_mfma_tflops": round(trk.trk_probe_mfma("fp8", 100_000), 1)}
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    out["hbm_copy_gbs"] = round(trk.trk_probe_copy(a, b, reps=5), 1)
+    del a, b
+    out["published"] = {"fp32_mfma_tflops": PEAK_TFLOPS["fp32"], "bf16_mfma_tflops": PEAK_TFLOPS["bf16"],
+                        "fp8_mfma_tflops": PEAK_TFLOPS["fp8"], "hbm_gbs": HBM_PEAK_GBS}
+    return out
+
+
 def cpu_baseline(cfg, nets, x):
     """FP64 oracle on a bounded sample of one event, scaled to events/s:
     embedding on 1/8 of the hits, the radius graph in full, the filter on 1/16
@@ -465,6 +480,16 @@ def main():
                 "candidate_jaccard_vs_primary": round(float(np.mean([a[1] for a in agr])), 5),
                 "n_cand_edges": int(nc2), "n_filt_edges": int(np.mean([i["n_filt_edges"] for i in inf2])),
             }
+    # roofline denominators measured on this device, beside the published peaks
+    try:
+        pm = measured_peaks(torch, trk)
+        result["peaks_measured"] = pm
+        key = {"fp32": "fp32_mfma_tflops", "bf16x3": "bf16_mfma_tflops", "bf16x3gnn16": "bf16_mfma_tflops",
+               "fp8": "fp8_mfma_tflops", "fp8all": "fp8_mfma_tflops"}.get(args.precision, "bf16_mfma_tflops")
+        result["roofline"]["peak_measured"] = pm[key]
+        result["roofline"]["frac_measured"] = round(filt_tflops / pm[key], 4)
+    except trk.TrkError as e:
+        result["peaks_measured"] = {"error": str(e)}
     if args.serve_seconds > 0:
         try:
             result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)

@@ -240,6 +240,22 @@ int trk_server_stats(trk_server* srv, trk_server_info* out);
 void trk_server_destroy(trk_server* srv);
 
 /* ------------------------------------------------------------------------
+ * Roofline denominators measured on the device (not part of the chain; the
+ * benchmark reports its fractions against these beside the spec-sheet peaks).
+ * trk_probe_mfma: dense matrix-core rate of `precision` (TRK_FP32, TRK_BF16 or
+ *   TRK_FP8: the v_mfma_f32_16x16x4_f32, 16x16x32_bf16 and 16x16x128 E4M3 forms the
+ *   kernels use) from independent MFMA chains on every CU, `iters` steps each;
+ *   *tflops (host) receives FLOP/s / 1e12.  Synchronous; allocates and frees a
+ *   small result buffer.  TRK_E_INVAL for another precision or iters < 1.
+ * trk_probe_copy: HBM bandwidth of a coalesced 16-byte copy of `bytes` (a
+ *   multiple of 16, both pointers 16-byte aligned, device, caller-owned) from
+ *   d_src to d_dst, `reps` times on `stream`; *gbps (host) = 2 * bytes * reps /
+ *   time / 1e9 (read plus write).  Synchronises the stream.
+ * ---------------------------------------------------------------------- */
+int trk_probe_mfma(int device_id, int precision, int64_t iters, double* tflops);
+int trk_probe_copy(const void* d_src, void* d_dst, size_t bytes, int reps, hipStream_t stream, double* gbps);
+
+/* ------------------------------------------------------------------------
  * Downstream helix fit of track candidates (what consumes the chain's output,
  * Section 2.2.2): every label value carried by at least min_hits spacepoints of
  * d_x[n][3] (the chain's features, rho/1000 mm, phi/pi, z/1000 mm) is a candidate.

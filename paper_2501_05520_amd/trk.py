@@ -25,7 +25,7 @@ EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_fil
            "trk_server_destroy", "trk_train_param_count", "trk_train_set_params", "trk_filter_train_fwd",
            "trk_filter_train_bwd", "trk_gnn_train_fwd", "trk_gnn_train_bwd", "trk_bce_with_logits",
            "trk_adam_update", "trk_embed_train_fwd", "trk_embed_train_bwd", "trk_pair_loss",
-           "trk_service_start", "trk_service_stop", "trk_fit")
+           "trk_service_start", "trk_service_stop", "trk_fit", "trk_probe_mfma", "trk_probe_copy")
 
 
 class TrkError(RuntimeError):
@@ -127,6 +127,9 @@ def lib():
             if name not in ("trk_destroy", "trk_strerror", "trk_server_destroy", "trk_service_stop"):
                 getattr(L, name).restype = ctypes.c_int
         L.trk_train_param_count.restype = ctypes.c_int64
+        L.trk_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+        L.trk_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -576,3 +579,25 @@ def trk_pair_loss(ctx, emb, pa, pb, y, margin, demb, neg_weight=1.0, stream=None
     _check(lib().trk_pair_loss(ctx, _ptr(emb), emb.shape[0], _ptr(pa), _ptr(pb), _ptr(y), pa.numel(), float(margin),
                                float(neg_weight), _ptr(demb), ctypes.byref(loss), _stream(stream)), "trk_pair_loss")
     return loss.value
+
+
+# ---------------------------------------------------------------------------
+# roofline denominators measured on the device
+# ---------------------------------------------------------------------------
+def trk_probe_mfma(precision, iters, device=0):
+    """Dense MFMA rate (TFLOP/s) of 'fp32', 'bf16' or 'fp8' measured on `device`."""
+    prec = {"fp32": TRK_FP32, "bf16": TRK_BF16, "fp8": TRK_FP8}[precision]
+    out = ctypes.c_double()
+    _check(lib().trk_probe_mfma(int(device), prec, int(iters), ctypes.byref(out)), "trk_probe_mfma")
+    return out.value
+
+
+def trk_probe_copy(src, dst, reps=5, stream=None):
+    """HBM GB/s (read + write) of a device-to-device copy of src into dst (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    out = ctypes.c_double()
+    _check(lib().trk_probe_copy(_ptr(src), _ptr(dst), nbytes, int(reps), _stream(stream), ctypes.byref(out)),
+           "trk_probe_copy")
+    return out.value
