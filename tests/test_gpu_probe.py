@@ -18,12 +18,16 @@ def test_mfma_probe(precision, iters):
     assert 0.3 * SPEC[precision] <= t <= 1.05 * SPEC[precision]
 
 
-def test_copy_probe():
+@pytest.mark.parametrize("n", [64 << 20, (64 << 20) + 12, 4])
+def test_copy_probe(n):
+    # distinct words, so that a copy to the wrong place is seen; sizes with and
+    # without a tail past the four-load steps, and a single 16-byte unit
     from paper_2501_05520_amd import trk
-    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-    b = torch.zeros_like(a)
+    a = torch.arange(n, dtype=torch.int32, device="cuda")
+    b = torch.full_like(a, -1)
     g = trk.trk_probe_copy(a, b, reps=3)
     torch.cuda.synchronize()
-    print(f"copy: {g:.0f} GB/s")
+    print(f"copy of {4 * n} bytes: {g:.0f} GB/s")
     assert torch.equal(a, b)
-    assert 1000.0 <= g <= 8000.0
+    if n >= 1 << 20:
+        assert 1000.0 <= g <= 8000.0
