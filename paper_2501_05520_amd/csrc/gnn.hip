@@ -624,12 +624,14 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
 // LDS and let more workgroups share a CU; eight-wave workgroups on 64 edges halve the
 // weight reads per edge.  The default (8) is 64 edges on eight waves with the edge
 // kernel's registers held to four waves per SIMD, so that two workgroups share a CU
-// in every precision (measured best, or level with variant 6, in FP32, BF16 and split
-// BF16).  TRK_GNN_TILE overrides.
+// in every precision (measured best, or level with variant 6, in FP32 and BF16).
+// Split BF16 takes variant 9, the same edge kernel with 32-node tiles for the node
+// step (whose registers then allow two workgroups per CU; 0.5-2 % faster there, level in
+// FP32, 1 % slower in BF16).  TRK_GNN_TILE overrides.
 template <class P>
 int gnn_tile_variant() {
   const char* e = getenv("TRK_GNN_TILE");
-  return e ? atoi(e) : 8;
+  return e ? atoi(e) : std::is_same<P, PrecX3>::value ? 9 : 8;
 }
 
 template <class P>
@@ -642,6 +644,7 @@ void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const 
     case 5: run_gnn<P, 128, 64, 32, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     case 6: run_gnn<P, 128, 64, 64, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     case 8: run_gnn<P, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
+    case 9: run_gnn<P, 128, 64, 32, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
     default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
   }
 }
