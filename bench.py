@@ -320,7 +320,7 @@ def train_measure(cfg, nets, steps, torch, trk, precision="fp32"):
     event per step (seeds 10000+step), BCE on generator truth, hand-written
     backward with per-iteration recomputation, Adam; edge sets from the FP32
     inference path.  Reports the step time and the device memory the training
-    context holds (from the driver's free-memory counter)."""
+    context holds (from HIP's free-memory counter)."""
     from gen import generate_event
     from paper_2501_05520_amd.training import TrainContext, train_step, edge_truth
     pipe = trk.Pipeline(cfg, nets, "fp32", max_hits=120000)
@@ -410,7 +410,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the tracking chain shards by whole events with no exchange "
-              f"between GPUs, and this build measures a single MI355X (--gpus {args.gpus} requested)",
+              f"between GPUs, and this benchmark measures a single MI355X (--gpus {args.gpus} requested)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -1,5 +1,5 @@
 """The socket front end (paper_2501_05520_amd/csrc/service_core.h) on the CPU: a
-C++ driver built with g++ under ThreadSanitizer and AddressSanitizer (16 client
+C++ test program built with g++ under ThreadSanitizer and AddressSanitizer (16 client
 connections, requests of random sizes including empty ones, protocol errors,
 shutdown with an open connection) and the Python client of trk.py against the
 same service in serve mode."""
