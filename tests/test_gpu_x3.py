@@ -4,7 +4,9 @@ FP64 oracle, held to the FP32 bars: scores within 1e-4, labels identical away
 from the cuts.  The embedding carries the split's own error (each operand within
 2^-18 relatively, against 2^-24 for FP32), so it gets a looser bound, and the
 candidate graph is compared on the oracle's own embedding (stage-isolated).  At
-pile-up 200 the chain's labels are compared with the FP32 chain's."""
+pile-up 200 the embedding of every hit, sampled filter scores and a one-step
+interaction network on ~1M edges are checked against the oracle at the same bars,
+and the chain's labels are compared with the FP32 chain's."""
 import numpy as np
 import pytest
 import torch
@@ -152,3 +154,57 @@ def test_mu200_agrees_with_fp32(precision):
           f"{ix['n_filt_edges']} vs {i32['n_filt_edges']}, kept {ix['n_kept_edges']} vs {i32['n_kept_edges']}; "
           f"hit agreement {hit:.5f} jaccard {jac:.4f}")
     assert hit >= 0.999
+
+
+# ------------------------------------------------- pile-up 200, sampled against the oracle
+@pytest.fixture(scope="module")
+def full_x3():
+    from paper_2501_05520_amd.trk import Pipeline
+    nets = make_weights(MU200, 0)
+    ev = generate_event(200, MU200.n_collisions)
+    p = Pipeline(MU200, nets, "bf16x3", max_hits=ev.n)
+    yield nets, ev, oracle.embed(ev.x, nets), p
+    p.close()
+
+
+def test_full_embed_every_hit(full_x3):
+    """The split-BF16 embedding of all 110,000 hits against the FP64 oracle."""
+    nets, ev, emb_ref, p = full_x3
+    emb = p.embed(ev.x).cpu().numpy()
+    de = np.abs(emb - emb_ref) / np.maximum(1.0, np.abs(emb_ref))
+    print(f"bf16x3 mu=200 embedding: rel max {de.max():.3g}, p99 {np.percentile(de, 99):.3g}")
+    assert de.max() <= EMB_TOL
+
+
+def test_full_filter_sampled(full_x3):
+    """Split-BF16 filter scores at full size (the candidate graph of the oracle's
+    embedding, ~3M edges), 20,000 sampled edges against the oracle at the FP32 bar."""
+    nets, ev, emb_ref, p = full_x3
+    e32 = emb_ref.astype(np.float32)
+    src, dst, _ = p.build_graph(e32)
+    src, dst = src.cpu().numpy(), dst.cpu().numpy()
+    sc = p.filter(e32, src, dst)[0].cpu().numpy()
+    idx = np.sort(np.random.default_rng(5).choice(src.size, 20000, replace=False))
+    ref = oracle.filter_scores(e32, src[idx], dst[idx], nets)
+    print(f"bf16x3 mu=200 filter: {src.size} edges, sampled |dp| max {np.abs(sc[idx] - ref).max():.3g}")
+    assert src.size > 2_000_000
+    assert np.abs(sc[idx] - ref).max() <= SCORE_TOL
+
+
+def test_full_gnn_one_iteration(full_x3):
+    """The split-BF16 interaction-network kernels at full size (~1M edges, one
+    message-passing step), every score against the oracle at the FP32 bar."""
+    from paper_2501_05520_amd.trk import Pipeline
+    nets, ev, emb_ref, p = full_x3
+    e32 = emb_ref.astype(np.float32)
+    src, dst, _ = p.build_graph(e32)
+    fs, fd = src.cpu().numpy()[::3], dst.cpu().numpy()[::3]
+    cfg1 = MU200.with_(gnn_iters=1)
+    nets1 = make_weights(cfg1, 0)
+    p1 = Pipeline(cfg1, nets1, "bf16x3", max_hits=ev.n, max_cand_edges=4_000_000, max_kept_edges=4_000_000)
+    q = p1.gnn(ev.x, fs, fd).cpu().numpy()
+    p1.close()
+    q_ref = oracle.interaction_network(ev.x, fs, fd, nets1, 1)
+    print(f"bf16x3 mu=200 gnn (1 step, {fs.size} edges): |dp| max {np.abs(q - q_ref).max():.3g}")
+    assert fs.size > 900_000
+    assert np.abs(q - q_ref).max() <= SCORE_TOL
