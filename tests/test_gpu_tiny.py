@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from gen import TINY, make_weights, generate_event, pack_events
+from gen import TINY, MU200, make_weights, generate_event, pack_events
 from tests.gpu_helpers import compare_edges, label_agreement
 
 pytestmark = pytest.mark.gpu
@@ -204,6 +204,42 @@ def test_edge_cases(pipe):
     with pytest.raises(trk.TrkError) as e:
         pipe.components(4, [0, 7], [1, 2], None)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16emb32", "bf16x3", "bf16x3gnn16", "fp8", "fp8all"])
+def test_edge_cases_every_precision(nets, ref, precision):
+    """The degenerate cases in every precision's kernels: an empty event, a single hit,
+    the interaction network with no edge, and a filter cut that no score passes (every
+    spacepoint is then its own component).  The FP8 forms need hidden widths in blocks
+    of 128 (a context with the tiny network is refused), so they run on the full-size
+    network with a pile-up-1 event."""
+    from paper_2501_05520_amd.trk import Pipeline
+    if precision.startswith("fp8"):
+        cfg, nw, ev = MU200, make_weights(MU200, 0), generate_event(2, 1)
+    else:
+        cfg, nw, ev = TINY, nets, ref[2][0]
+    p = Pipeline(cfg, nw, precision, max_hits=8192)
+    labels, info = p.event(np.zeros((0, 3), np.float32))
+    assert labels.numel() == 0 and info["n_hits"] == 0
+    labels, info = p.event(np.array([[0.5, 0.1, 0.2]], np.float32))
+    assert labels.cpu().tolist() == [0] and info["n_cand_edges"] == 0
+    assert p.gnn(np.zeros((4, 3), np.float32), [], []).numel() == 0
+    p.close()
+    q = Pipeline(cfg.with_(filter_cut=1.0), nw, precision, max_hits=8192)
+    labels, info = q.event(ev.x)
+    q.close()
+    assert info["n_filt_edges"] == 0 and info["n_kept_edges"] == 0
+    assert np.array_equal(labels.cpu().numpy(), np.arange(ev.n))
+
+
+def test_fp8_refuses_the_tiny_network(nets):
+    """FP8 products take k in blocks of 128: a context whose filter (or embedding)
+    hidden width is 64 is refused with TRK_E_INVAL instead of being run."""
+    from paper_2501_05520_amd import trk
+    for precision in ("fp8", "fp8all"):
+        with pytest.raises(trk.TrkError) as e:
+            trk.Pipeline(TINY, nets, precision, max_hits=8192)
+        assert e.value.status == -1
 
 
 def test_capacity_reported(pipe, ref):
