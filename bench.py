@@ -354,6 +354,18 @@ def train_measure(cfg, nets, steps, torch, trk, precision="fp32"):
                                   "and stored states"}[precision]}
 
 
+# The paper's own figures for its served chain (Section 4), on its hardware and workload:
+# context only, not comparable (trained models of unstated precision on ~350k ACTS
+# spacepoints per event, with the connected components on the CPU).
+PAPER_CONTEXT = {
+    "hardware": "one NVIDIA A100-SXM4 behind Triton (Perlmutter)",
+    "workload": "ttbar at mu=200, about 350k spacepoints per event, trained models",
+    "max_throughput_events_per_s": 1.75,
+    "seconds_per_event": {"cpu_direct": 9.65, "gpu_direct": 2.42, "gpu_as_a_service": 2.24},
+    "comparable": False,
+}
+
+
 def measured_peaks(torch, trk):
     """Dense MFMA rate of each precision from independent MFMA chains on every CU,
     and the HBM bandwidth of a 1 GiB device-to-device copy (read + write)."""
@@ -540,6 +552,7 @@ def main():
             result["training_bf16"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, nets, xs[0])
+    result["paper_context"] = PAPER_CONTEXT
     print(json.dumps(result), flush=True)
 
 
