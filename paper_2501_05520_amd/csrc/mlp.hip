@@ -93,7 +93,10 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
 }
 
 // Filter: scores[e] = sigmoid(out . tanh(L_last(... tanh(L_in([emb_src, emb_dst]))))).
-template <class P, class P0, int W, int MT, int NW>
+// GPF: the next tile's gathered inputs are requested during the last layer's epilogue
+// (edge ends first, under the epilogue's arithmetic; then the embedding values), so
+// that the tile start does not wait for two dependent round trips to memory.
+template <class P, class P0, int W, int MT, int NW, bool GPF = false>
 __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict__ emb, int D,
                                                          const int* __restrict__ src, const int* __restrict__ dst,
                                                          int64_t m_host, const int* __restrict__ d_m, int64_t cap,
@@ -114,18 +117,59 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
   const int nlayers = 1 + hid.n;
   const int kin = 2 * D;
   const int kin_pad = l_in.nkb * P0::KB;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t row0 = t * MT;
-    for (int idx = threadIdx.x; idx < MT * kin_pad; idx += blockDim.x) {
+  // the gathered inputs held in registers between tiles (GPF): this thread's entries
+  // idx = threadIdx.x + i * blockDim.x of the MT x kin_pad input tile
+  constexpr int GI = (MT * KIN_MAX + NW * 64 - 1) / (NW * 64);
+  int gnd[GI];
+  bool gok[GI];
+  float gv[GI];
+  auto gather_ends = [&](int64_t r0) {
+#pragma unroll
+    for (int i = 0; i < GI; ++i) {
+      const int idx = threadIdx.x + i * NW * 64;
       const int mm = idx / kin_pad, k = idx - mm * kin_pad;
-      const int64_t e = row0 + mm;
-      float v = 0.f;
-      if (e < m && k < kin) {
-        const int node = (k < D) ? src[e] : dst[e];
-        if ((unsigned)node < (unsigned)n_nodes) v = emb[(size_t)node * D + (k < D ? k : k - D)];
+      const int64_t e = r0 + mm;
+      gok[i] = idx < MT * kin_pad && e < m && k < kin;
+      gnd[i] = gok[i] ? ((k < D) ? src[e] : dst[e]) : 0;
+    }
+  };
+  auto gather_values = [&]() {
+#pragma unroll
+    for (int i = 0; i < GI; ++i) {
+      const int idx = threadIdx.x + i * NW * 64;
+      const int k = idx % kin_pad;
+      gv[i] = 0.f;
+      if (gok[i]) {
+        if ((unsigned)gnd[i] < (unsigned)n_nodes) gv[i] = emb[(size_t)gnd[i] * D + (k < D ? k : k - D)];
         else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
       }
-      xin[mm * S::LDI + k] = P0::cvt(v);
+    }
+  };
+  if (GPF && (int64_t)blockIdx.x < ntiles) {
+    gather_ends((int64_t)blockIdx.x * MT);
+    gather_values();
+  }
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * MT;
+    if constexpr (GPF) {
+#pragma unroll
+      for (int i = 0; i < GI; ++i) {
+        const int idx = threadIdx.x + i * NW * 64;
+        const int mm = idx / kin_pad, k = idx - mm * kin_pad;
+        if (idx < MT * kin_pad) xin[mm * S::LDI + k] = P0::cvt(gv[i]);
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < MT * kin_pad; idx += blockDim.x) {
+        const int mm = idx / kin_pad, k = idx - mm * kin_pad;
+        const int64_t e = row0 + mm;
+        float v = 0.f;
+        if (e < m && k < kin) {
+          const int node = (k < D) ? src[e] : dst[e];
+          if ((unsigned)node < (unsigned)n_nodes) v = emb[(size_t)node * D + (k < D ? k : k - D)];
+          else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+        }
+        xin[mm * S::LDI + k] = P0::cvt(v);
+      }
     }
     __syncthreads();
     for (int layer = 0; layer < nlayers; ++layer) {
@@ -145,11 +189,19 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
         const float sc = L.dq * TRK_2LOG2E;
 #pragma unroll
         for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
+        float4 bq[S::NTW], wq[S::NTW];
 #pragma unroll
         for (int j = 0; j < S::NTW; ++j) {
           const int n = (nt0 + j) * 16 + 4 * g;
-          const float4 b = *(const float4*)(L.bs + n);
-          const float4 w = *(const float4*)(out.w + n);
+          bq[j] = *(const float4*)(L.bs + n);
+          wq[j] = *(const float4*)(out.w + n);
+        }
+        // the next tile's edge ends, requested after every load this epilogue waits for
+        if constexpr (GPF) gather_ends(row0 + (int64_t)gridDim.x * MT);
+#pragma unroll
+        for (int j = 0; j < S::NTW; ++j) {
+          const float4 b = bq[j];
+          const float4 w = wq[j];
 #pragma unroll
           for (int i = 0; i < S::MTW; ++i) {
             const f32x4 a = acc[i][j];
@@ -164,6 +216,7 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
           if (g == 0) zred[wave * MT + i * 16 + r] = part[i];
         }
         __syncthreads();
+        if constexpr (GPF) gather_values();
         for (int mm = threadIdx.x; mm < MT; mm += blockDim.x) {
           float z = out.b;
           for (int w = 0; w < NW; ++w) z += zred[w * MT + mm];
@@ -184,7 +237,7 @@ void launch_embed_t(const float* x, int n, const DevLayer& l_in, const LayerList
   embed_kernel<P, P0, W, MT, NW><<<grid, NW * 64, 0, s>>>(x, n, l_in, hid, l_out, D, emb);
 }
 
-template <class P, class P0, int W, int MT, int NW>
+template <class P, class P0, int W, int MT, int NW, bool GPF = false>
 void launch_filter_t(const float* emb, int D, const int* src, const int* dst, int64_t m_host, const int* d_m,
                      int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out, float* scores,
                      int n_nodes, int* d_err, int max_grid, hipStream_t s) {
@@ -192,14 +245,16 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
   const int64_t ntiles = (m + MT - 1) / MT;
   const int grid = (int)(ntiles < max_grid ? ntiles : max_grid);
   if (grid <= 0) return;
-  filter_kernel<P, P0, W, MT, NW><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
+  filter_kernel<P, P0, W, MT, NW, GPF><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
 }
 
 // Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
-// the faster shape on MI355X), 1 = two 4-wave workgroups per CU with half the rows
-// (FP8: the other row-tile height of the 8-wave workgroup), 2 = FP32 only: two
-// 8-wave workgroups per CU with half the rows, so that one workgroup's epilogue
-// and barriers overlap the other's products.
+// the faster shape on MI355X; the FP32 filter requests the next tile's inputs during
+// its last epilogue), 1 = two 4-wave workgroups per CU with half the rows (FP8: the
+// other row-tile height of the 8-wave workgroup), 2 = FP32 only: two 8-wave
+// workgroups per CU with half the rows, so that one workgroup's epilogue and barriers
+// overlap the other's products, 5 = the FP32 filter of 0 with the inputs gathered at
+// the start of each tile.
 int tile_variant() {
   const char* e = getenv("TRK_MLP_TILE");
   return e ? atoi(e) : 0;
@@ -232,7 +287,8 @@ int launch_filter(int prec, int W, const float* emb, int D, const int* src, cons
                   const int* d_m, int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out,
                   float* scores, int n_nodes, int* d_err, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 5) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8, false>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 512 && tile_variant() == 2) { launch_filter_t<PrecF32, PrecF32, 512, 32, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 512) { launch_filter_t<PrecF32, PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
     if (W == 64) { launch_filter_t<PrecF32, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
