@@ -249,12 +249,12 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
 }
 
 // Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
-// the faster shape on MI355X; the FP32 and split-BF16 filters request the next tile's
-// inputs during their last epilogue), 1 = two 4-wave workgroups per CU with half the
-// rows (FP8: the other row-tile height of the 8-wave workgroup), 2 = FP32 only: two
+// the faster shape on MI355X; the FP32, split-BF16 and FP8 filters request the next
+// tile's inputs during their last epilogue), 1 = two 4-wave workgroups per CU with half
+// the rows (FP8: the other row-tile height of the 8-wave workgroup), 2 = FP32 only: two
 // 8-wave workgroups per CU with half the rows, so that one workgroup's epilogue and
-// barriers overlap the other's products, 5 = the FP32 and split-BF16 filters of 0 with
-// the inputs gathered at the start of each tile.
+// barriers overlap the other's products, 5 = the FP32, split-BF16 and FP8 filters of 0
+// with the inputs gathered at the start of each tile.
 int tile_variant() {
   const char* e = getenv("TRK_MLP_TILE");
   return e ? atoi(e) : 0;
@@ -297,7 +297,8 @@ int launch_filter(int prec, int W, const float* emb, int D, const int* src, cons
     if (W == 512) { launch_filter_t<PrecX3, PrecF32, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 64) { launch_filter_t<PrecX3, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 5) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8, false>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 512) { launch_filter_t<PrecFP8, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
   } else {
     if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecBF16, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
