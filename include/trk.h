@@ -128,7 +128,10 @@ typedef struct {
 int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int device_id,
                trk_ctx** out);
 
-/* Waits for the context's work and frees everything it owns.  NULL is a no-op. */
+/* Waits for the work this context enqueued (not for other contexts or streams) and
+ * frees everything it owns.  NULL is a no-op.  Calls on one context are ordered:
+ * a call on a stream other than the previous call's waits for that call's work,
+ * since both use the context's scratch memory. */
 void trk_destroy(trk_ctx* ctx);
 
 /* Embedding (Section 2.2.2): d_emb[n][emb_dim] = MLP_emb(d_x[n][3]).  0 <= n <= max_hits. */

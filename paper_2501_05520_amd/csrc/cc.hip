@@ -149,11 +149,8 @@ __global__ void uf_compress(int* parent, int n) {
   }
 }
 
-// atomicMin rounds before the compare-and-swap pass (TRK_UF_ROUNDS overrides)
-int uf_rounds() {
-  const char* v = getenv("TRK_UF_ROUNDS");
-  return v ? atoi(v) : 4;
-}
+// atomicMin rounds before the compare-and-swap pass
+constexpr int kHookRounds = 4;
 
 }  // namespace
 
@@ -166,7 +163,7 @@ void launch_components(int n, const int* src, const int* dst, const float* score
     // the initial forest has chains of decreasing ids; pointing every spacepoint at
     // the end of its chain first keeps the finds of the union pass short
     uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
-    for (int round = 0; round < uf_rounds(); ++round) {
+    for (int round = 0; round < kHookRounds; ++round) {
       uf_hook_min<<<blocks_for(m_cap, 256, 2048), 256, 0, s>>>(labels, src, dst, scores, cut, m_cap, d_m, n);
       uf_compress<<<blocks_for(n, 256), 256, 0, s>>>(labels, n);
     }

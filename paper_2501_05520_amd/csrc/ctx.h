@@ -44,7 +44,6 @@ struct trk_ctx {
   int prec = TRK_PREC_F32;       // filter MLP
   int prec_emb = TRK_PREC_F32;   // embedding MLP
   int prec_gnn = TRK_PREC_F32;   // interaction network
-  hipStream_t own_stream = nullptr;
   // weights
   void* wmem = nullptr;
   DevLayer emb_in, emb_out;
@@ -78,7 +77,29 @@ struct trk_ctx {
   int* host_counts = nullptr;    // pinned per-event counts [max_events][4]
   hipEvent_t ev_stage[8] = {};
   bool timing = false;
+  // the last call's completion and its stream (see CtxStreamScope)
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool used = false;
   TrainState* train = nullptr;   // training buffers (trk_config.training != 0)
+};
+
+// Every entry point that enqueues work on a context holds one of these for the call:
+// a call on a stream other than the previous call's first waits for that call's work
+// (both would use the context's scratch), and the call's completion is recorded, so
+// that trk_destroy waits for this context's own work only.
+struct CtxStreamScope {
+  trk_ctx* c;
+  hipStream_t s;
+  CtxStreamScope(trk_ctx* c_, hipStream_t s_) : c(c_), s(s_) {
+    if (c->done && c->used && c->last_stream != s) hipStreamWaitEvent(s, c->done, 0);
+  }
+  ~CtxStreamScope() {
+    if (c->done && hipEventRecord(c->done, s) == hipSuccess) {
+      c->last_stream = s;
+      c->used = true;
+    }
+  }
 };
 
 // training (train.hip)

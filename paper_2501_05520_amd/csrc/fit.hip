@@ -236,6 +236,7 @@ extern "C" int trk_fit(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d
                        double b_field, int32_t* d_cand_label, int32_t* d_cand_nhits, double* d_params, int64_t cap,
                        int64_t* n_cands, hipStream_t s) {
   if (!c || n < 0 || n > c->cfg.max_hits || min_hits < 1 || cap < 0 || !n_cands) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n > 0 && (!d_x || !d_labels)) return TRK_E_INVAL;
   if (cap > 0 && (!d_cand_label || !d_cand_nhits || !d_params)) return TRK_E_INVAL;
   *n_cands = 0;

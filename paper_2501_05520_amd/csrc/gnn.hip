@@ -568,16 +568,9 @@ __global__ void incidence_fill(const int* __restrict__ key, int64_t m_cap, const
   }
 }
 
-// Grid of the aggregation: by default one node per wave up to 65536 four-wave
-// blocks (waves that finish early are replaced at once, which balances uneven
-// degrees; measured faster than two nodes per wave and than a persistent grid);
-// TRK_GNN_AGG=1 gives a persistent grid of one full-occupancy set of waves walking
-// the nodes, TRK_GNN_AGG=b > 1 a cap of b blocks.
-int agg_blocks(int n, int n_cu) {
-  const char* v = getenv("TRK_GNN_AGG");
-  const int a = v ? atoi(v) : 0;
-  return blocks_for(n, 4, a == 1 ? n_cu * 8 : a > 1 ? a : 65536);
-}
+// Grid of the aggregation: one node per wave, up to 65536 four-wave blocks (waves that
+// finish early are replaced at once, which balances uneven degrees).
+int agg_blocks(int n) { return blocks_for(n, 4, 65536); }
 
 // the unrolled products read ceil(K / KB) fragment blocks per n-tile of each layer
 template <class P, int H>
@@ -611,7 +604,7 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
       edge_kernel<P, H, MTE, NW, false, EWPE><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
                                                                   net.edge_2, net.out_2, nullptr);
     const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
-    aggregate_kernel<P, H><<<agg_blocks(n, n_cu), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
+    aggregate_kernel<P, H><<<agg_blocks(n), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
     if (ngrid > 0)
       node_step_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
   }
@@ -620,33 +613,17 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
                                                                net.edge_2, net.out_2, scores);
 }
 
-// Row tiles of the H=128 kernels (edge tile, node tile, waves): smaller tiles use less
-// LDS and let more workgroups share a CU; eight-wave workgroups on 64 edges halve the
-// weight reads per edge.  The default (8) is 64 edges on eight waves with the edge
-// kernel's registers held to four waves per SIMD, so that two workgroups share a CU
-// in every precision (measured best, or level with variant 6, in FP32 and BF16).
-// Split BF16 takes variant 9, the same edge kernel with 32-node tiles for the node
-// step (whose registers then allow two workgroups per CU; 0.5-2 % faster there, level in
-// FP32, 1 % slower in BF16).  TRK_GNN_TILE overrides.
-template <class P>
-int gnn_tile_variant() {
-  const char* e = getenv("TRK_GNN_TILE");
-  return e ? atoi(e) : std::is_same<P, PrecX3>::value ? 9 : 8;
-}
-
+// Row tiles of the H=128 kernels: 64-edge tiles on eight waves with the edge kernel's
+// registers held to four waves per SIMD, so that two workgroups share a CU; 64-node tiles
+// for the node step, except in split BF16, whose node step takes 32-node tiles (its
+// registers then also allow two workgroups per CU).
 template <class P>
 void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
                 const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool sorted) {
-  switch (gnn_tile_variant<P>()) {
-    case 0: run_gnn<P, 128, 64, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    case 2: run_gnn<P, 128, 32, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    case 3: run_gnn<P, 128, 32, 64, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    case 5: run_gnn<P, 128, 64, 32, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    case 6: run_gnn<P, 128, 64, 64, 8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    case 8: run_gnn<P, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    case 9: run_gnn<P, 128, 64, 32, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-    default: run_gnn<P, 128, 64, 32, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted); break;
-  }
+  if (std::is_same<P, PrecX3>::value)
+    run_gnn<P, 128, 64, 32, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
+  else
+    run_gnn<P, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
 }
 
 }  // namespace

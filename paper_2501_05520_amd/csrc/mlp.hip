@@ -248,61 +248,44 @@ void launch_filter_t(const float* emb, int D, const int* src, const int* dst, in
   filter_kernel<P, P0, W, MT, NW, GPF><<<grid, NW * 64, 0, s>>>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err);
 }
 
-// Tile shape of the wide layers: 0 = one 8-wave workgroup per CU (large row tile,
-// the faster shape on MI355X; the FP32, split-BF16 and FP8 filters request the next
-// tile's inputs during their last epilogue), 1 = two 4-wave workgroups per CU with half
-// the rows (FP8: the other row-tile height of the 8-wave workgroup), 2 = FP32 only: two
-// 8-wave workgroups per CU with half the rows, so that one workgroup's epilogue and
-// barriers overlap the other's products, 5 = the FP32, split-BF16 and FP8 filters of 0
-// with the inputs gathered at the start of each tile.
-int tile_variant() {
-  const char* e = getenv("TRK_MLP_TILE");
-  return e ? atoi(e) : 0;
-}
-
 }  // namespace
 
+// One tile shape per precision and width: eight-wave workgroups (one per CU) on 32
+// rows (FP32, split BF16, FP8) or 64 rows (BF16) at the full width, four waves on 64
+// rows at the tiny width.  Any other width is refused.
 int launch_embed(int prec, int W, const float* x, int n, const DevLayer& l_in, const LayerList& hid,
                  const DevLayer& l_out, int D, float* emb, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecF32, PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
-    if (W == 1024 && tile_variant() == 2) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 8>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
-    if (W == 1024) { launch_embed_t<PrecF32, PrecF32, 1024, 16, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecF32, PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
     if (W == 64) { launch_embed_t<PrecF32, PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_X3) {
     if (W == 1024) { launch_embed_t<PrecX3, PrecF32, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
     if (W == 64) { launch_embed_t<PrecX3, PrecF32, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {
-    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecFP8, PrecBF16, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
-    if (W == 1024) { launch_embed_t<PrecFP8, PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecFP8, PrecBF16, 1024, 32, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
   } else {
-    if (W == 1024 && tile_variant() == 0) { launch_embed_t<PrecBF16, PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
-    if (W == 1024) { launch_embed_t<PrecBF16, PrecBF16, 1024, 32, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 2, s); return 0; }
+    if (W == 1024) { launch_embed_t<PrecBF16, PrecBF16, 1024, 64, 8>(x, n, l_in, hid, l_out, D, emb, n_cu, s); return 0; }
     if (W == 64) { launch_embed_t<PrecBF16, PrecBF16, 64, 64, 4>(x, n, l_in, hid, l_out, D, emb, n_cu * 4, s); return 0; }
   }
   return -1;
 }
 
+// The FP32, split-BF16 and FP8 filters at the full width run 64-edge tiles on eight
+// waves and request the next tile's gathered inputs during their last epilogue; the
+// BF16 filter runs 128-edge tiles (no registers are left for that prefetch).
 int launch_filter(int prec, int W, const float* emb, int D, const int* src, const int* dst, int64_t m_host,
                   const int* d_m, int64_t cap, const DevLayer& l_in, const LayerList& hid, const DevVec& out,
                   float* scores, int n_nodes, int* d_err, int n_cu, hipStream_t s) {
   if (prec == TRK_PREC_F32) {
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512 && tile_variant() == 5) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8, false>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512 && tile_variant() == 2) { launch_filter_t<PrecF32, PrecF32, 512, 32, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
-    if (W == 512) { launch_filter_t<PrecF32, PrecF32, 512, 32, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecF32, PrecF32, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 64) { launch_filter_t<PrecF32, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_X3) {
-    if (W == 512 && tile_variant() == 5) { launch_filter_t<PrecX3, PrecF32, 512, 64, 8, false>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 512) { launch_filter_t<PrecX3, PrecF32, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 64) { launch_filter_t<PrecX3, PrecF32, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   } else if (prec == TRK_PREC_FP8) {
-    if (W == 512 && tile_variant() == 5) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8, false>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512) { launch_filter_t<PrecFP8, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecFP8, PrecBF16, 512, 64, 8, true>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
   } else {
-    if (W == 512 && tile_variant() == 0) { launch_filter_t<PrecBF16, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
-    if (W == 512) { launch_filter_t<PrecBF16, PrecBF16, 512, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 2, s); return 0; }
+    if (W == 512) { launch_filter_t<PrecBF16, PrecBF16, 512, 128, 8>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu, s); return 0; }
     if (W == 64) { launch_filter_t<PrecBF16, PrecBF16, 64, 64, 4>(emb, D, src, dst, m_host, d_m, cap, l_in, hid, out, scores, n_nodes, d_err, n_cu * 4, s); return 0; }
   }
   return -1;

@@ -848,12 +848,14 @@ int64_t trk_train_param_count(const trk_config* cfg) {
 
 int trk_train_set_params(trk_ctx* c, const float* d_params, hipStream_t s) {
   if (!train_ready(c) || !d_params) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   return train_set_params(c, d_params, s);
 }
 
 int trk_filter_train_fwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, const int32_t* d_dst,
                          int64_t m, float* d_logits, hipStream_t s) {
   if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_c) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (m > 0 && (!d_emb || !d_src || !d_dst || !d_logits)) return TRK_E_INVAL;
   if (m == 0) return TRK_OK;
   TrainState& T = *c->train;
@@ -875,6 +877,7 @@ int trk_filter_train_fwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
 int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, const int32_t* d_dst,
                          int64_t m, const float* d_dlogits, float* d_grads, hipStream_t s) {
   if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_c || !d_grads) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (m > 0 && (!d_emb || !d_src || !d_dst || !d_dlogits)) return TRK_E_INVAL;
   if (m == 0) return TRK_OK;
   TrainState& T = *c->train;
@@ -901,6 +904,7 @@ int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
 int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const int32_t* d_dst, int64_t m,
                       float* d_logits, hipStream_t s) {
   if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_f || !d_x) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (m > 0 && (!d_src || !d_dst || !d_logits)) return TRK_E_INVAL;
   TrainState& T = *c->train;
   GnnScratch& g = c->gs;
@@ -943,6 +947,7 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
                       const float* d_dlogits, float* d_grads, hipStream_t s) {
   if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || m < 0 || m > c->train->cap_f || !d_x || !d_grads)
     return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (m > 0 && (!d_src || !d_dst || !d_dlogits)) return TRK_E_INVAL;
   TrainState& T = *c->train;
   GnnScratch& g = c->gs;
@@ -1015,6 +1020,7 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
 
 int trk_embed_train_fwd(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, hipStream_t s) {
   if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_emb))) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n == 0) return TRK_OK;
   TrainState& T = *c->train;
   const int EL = c->cfg.emb_layers, EW = c->cfg.emb_hidden, D = c->cfg.emb_dim;
@@ -1033,6 +1039,7 @@ int trk_embed_train_fwd(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, h
 
 int trk_embed_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const float* d_demb, float* d_grads, hipStream_t s) {
   if (!train_ready(c) || n < 0 || n > c->cfg.max_hits || !d_grads || (n > 0 && (!d_x || !d_demb))) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n == 0) return TRK_OK;
   TrainState& T = *c->train;
   const int EL = c->cfg.emb_layers, EW = c->cfg.emb_hidden, D = c->cfg.emb_dim;
@@ -1060,6 +1067,7 @@ int trk_pair_loss(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_pa
                   hipStream_t s) {
   if (!train_ready(c) || n < 1 || n > c->cfg.max_hits || npairs < 0 || npairs > c->train->cap_c || !d_emb || !d_demb)
     return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (npairs > 0 && (!d_pa || !d_pb || !d_y)) return TRK_E_INVAL;
   if (!(neg_weight >= 0.f) || !(margin >= 0.f)) return TRK_E_INVAL;
   TrainState& T = *c->train;
@@ -1090,6 +1098,7 @@ int trk_pair_loss(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_pa
 int trk_bce_with_logits(trk_ctx* c, const float* d_logits, const float* d_targets, int64_t m, float* d_dlogits,
                         float* h_loss, hipStream_t s) {
   if (!train_ready(c) || m < 0 || (m > 0 && (!d_logits || !d_targets || !d_dlogits))) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (h_loss) *h_loss = 0.f;
   if (m == 0) return TRK_OK;
   TrainState& T = *c->train;
@@ -1107,6 +1116,7 @@ int trk_bce_with_logits(trk_ctx* c, const float* d_logits, const float* d_target
 int trk_adam_update(trk_ctx* c, float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t count, float lr,
                     float beta1, float beta2, float eps, int64_t step, hipStream_t s) {
   if (!c || count < 0 || step < 1 || (count > 0 && (!d_params || !d_grads || !d_m || !d_v))) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
   if (count > 0) ew(adam_kernel, count, s, d_params, d_grads, d_m, d_v, count, lr, beta1, beta2, eps, c1, c2);
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;

@@ -427,6 +427,8 @@ const char* trk_strerror(int status) {
     case TRK_E_CAPACITY: return "edge count exceeds capacity";
     case TRK_E_DEVICE: return "HIP runtime error";
     case TRK_E_WEIGHTS: return "malformed weight blob";
+    case TRK_E_EXPIRED: return "request deadline passed before it was run";
+    case TRK_E_SHUTDOWN: return "server is shutting down";
     default: return "unknown status";
   }
 }
@@ -458,6 +460,7 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
   if (!rc) rc = alloc_scratch(c);
   c->timing = cfg->stage_timing != 0;
   if (!rc && cfg->training) rc = train_create(c);
+  if (!rc && hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) rc = TRK_E_DEVICE;
   for (int i = 0; i < 8 && !rc && c->timing; ++i)
     if (hipEventCreate(&c->ev_stage[i]) != hipSuccess) rc = TRK_E_DEVICE;
   if (rc) {
@@ -471,7 +474,12 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
 void trk_destroy(trk_ctx* c) {
   if (!c) return;
   DeviceGuard guard(c->device);
-  hipDeviceSynchronize();
+  // every call on this context is ordered after the previous one, so its last
+  // recorded completion covers all of its work (other contexts are not waited for)
+  if (c->done) {
+    if (c->used) hipEventSynchronize(c->done);
+    hipEventDestroy(c->done);
+  }
   train_destroy(c);
   if (c->arena.base) hipFree(c->arena.base);
   if (c->wmem) hipFree(c->wmem);
@@ -485,6 +493,7 @@ void trk_destroy(trk_ctx* c) {
 
 int trk_embed(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, hipStream_t s) {
   if (!c || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_emb))) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n == 0) return TRK_OK;
   DeviceGuard guard(c->device);
   if (launch_embed(c->prec_emb, c->cfg.emb_hidden, d_x, (int)n, c->emb_in, c->emb_hid, c->emb_out, c->cfg.emb_dim, d_emb,
@@ -496,6 +505,7 @@ int trk_embed(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, hipStream_t
 int trk_build_graph(trk_ctx* c, const float* d_emb, int64_t n, int32_t* d_src, int32_t* d_dst, int64_t cap,
                     int64_t* h_n_edges, int64_t* h_n_saturated, hipStream_t s) {
   if (!c || !h_n_edges || n < 0 || n > c->cfg.max_hits || cap < 0) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n > 0 && (!d_emb || (cap > 0 && (!d_src || !d_dst)))) return TRK_E_INVAL;
   *h_n_edges = 0;
   if (h_n_saturated) *h_n_saturated = 0;
@@ -516,6 +526,7 @@ int trk_filter(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, 
                float* d_scores, int32_t* d_kept_src, int32_t* d_kept_dst, int64_t cap, int64_t* h_n_kept,
                hipStream_t s) {
   if (!c || !h_n_kept || n < 0 || n > c->cfg.max_hits || m < 0 || cap < 0) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (m > 0 && (!d_emb || !d_src || !d_dst)) return TRK_E_INVAL;
   if (cap > 0 && (!d_kept_src || !d_kept_dst)) return TRK_E_INVAL;
   if (m > c->cfg.max_cand_edges) return TRK_E_INVAL;
@@ -539,6 +550,7 @@ int trk_filter(trk_ctx* c, const float* d_emb, int64_t n, const int32_t* d_src, 
 int trk_gnn(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const int32_t* d_dst, int64_t m,
             float* d_scores, hipStream_t s) {
   if (!c || n < 0 || n > c->cfg.max_hits || m < 0 || m > c->cfg.max_kept_edges) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n > 0 && !d_x) return TRK_E_INVAL;
   if (m > 0 && (!d_src || !d_dst || !d_scores)) return TRK_E_INVAL;
   if (n == 0) return m == 0 ? TRK_OK : TRK_E_INVAL;
@@ -554,6 +566,7 @@ int trk_gnn(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_src, const
 int trk_components(trk_ctx* c, int64_t n, const int32_t* d_src, const int32_t* d_dst, const float* d_scores,
                    int64_t m, float cut, int32_t* d_labels, hipStream_t s) {
   if (!c || n < 0 || n > c->cfg.max_hits || m < 0 || m > (1LL << 31) - 1) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n > 0 && !d_labels) return TRK_E_INVAL;
   if (m > 0 && (!d_src || !d_dst)) return TRK_E_INVAL;
   if (n == 0) return m == 0 ? TRK_OK : TRK_E_INVAL;
@@ -567,6 +580,7 @@ int trk_components(trk_ctx* c, int64_t n, const int32_t* d_src, const int32_t* d
 
 int trk_event(trk_ctx* c, const float* d_x, int64_t n, int32_t* d_labels, trk_event_info* info, hipStream_t s) {
   if (!c || n < 0 || n > c->cfg.max_hits || (n > 0 && (!d_x || !d_labels))) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (info) memset(info, 0, sizeof(*info));
   if (n == 0) return TRK_OK;
   DeviceGuard guard(c->device);
@@ -659,6 +673,7 @@ __global__ __launch_bounds__(256) void event_counts_kernel(const int64_t* __rest
 extern "C" int trk_batch(trk_ctx* c, int32_t n_events, const float* d_x, const int64_t* h_offsets, int32_t* d_labels,
                          trk_event_info* infos, hipStream_t s) {
   if (!c || n_events < 0 || n_events > c->cfg.max_events || (n_events > 0 && !h_offsets)) return TRK_E_INVAL;
+  CtxStreamScope scope(c, s);
   if (n_events == 0) return TRK_OK;
   if (h_offsets[0] != 0) return TRK_E_INVAL;
   for (int b = 0; b < n_events; ++b)

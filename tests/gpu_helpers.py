@@ -27,8 +27,9 @@ def kth_distance(emb, lo, hi, d2, k_max):
     return kth
 
 
-def compare_edges(emb, gsrc, gdst, osrc, odst, radius, k_max, lo, hi, d2):
-    """Returns (n_diff_total, n_diff_outside_bands, details)."""
+def compare_edges(emb, gsrc, gdst, osrc, odst, radius, k_max, lo, hi, d2, band=None):
+    """Returns (n_diff_total, n_diff_outside_bands, details).  `band` widens both
+    bands (default RADIUS_BAND and TIE_BAND)."""
     n = emb.shape[0]
     e = np.asarray(emb, np.float64)
     g = pair_keys(gsrc, gdst, n)
@@ -39,7 +40,9 @@ def compare_edges(emb, gsrc, gdst, osrc, odst, radius, k_max, lo, hi, d2):
     a, b = diff // n, diff % n
     d = np.sqrt(((e[a] - e[b]) ** 2).sum(axis=1))
     kth = kth_distance(e, lo, hi, d2, k_max)
-    in_band = (np.abs(d - radius) <= RADIUS_BAND) | (np.abs(d - kth[a]) <= TIE_BAND) | (np.abs(d - kth[b]) <= TIE_BAND)
+    rb = RADIUS_BAND if band is None else band
+    tb = TIE_BAND if band is None else band
+    in_band = (np.abs(d - radius) <= rb) | (np.abs(d - kth[a]) <= tb) | (np.abs(d - kth[b]) <= tb)
     bad = ~in_band
     details = [(int(x), int(y), float(z), bool(x * n + y in set(g.tolist()))) for x, y, z in
                zip(a[bad][:10], b[bad][:10], d[bad][:10])]

@@ -3,9 +3,10 @@
 configuration the benchmark times:
   * a pile-up-10 event (5,500 hits), small enough for the whole FP64 oracle:
     every stage stage-isolated and the chain end to end;
-  * the pile-up-200 event (110,000 hits): embedding on sampled hits, the radius
+  * the pile-up-200 event (110,000 hits): the embedding of every hit, the radius
     graph in full, filter scores on sampled edges, components in full, the
-    interaction network in full with one iteration, batch-vs-alone identity.
+    interaction network in full with one iteration, batch-vs-alone identity, and
+    the whole chain end to end against the whole FP64 oracle.
 BF16 runs report their error against the oracle and assert only sanity bounds."""
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ import torch
 
 import oracle
 from gen import MU200, make_weights, generate_event, pack_events
+from tests.chain_parity import chain_parity
 from tests.gpu_helpers import compare_edges, label_agreement
 
 pytestmark = pytest.mark.gpu
@@ -77,19 +79,13 @@ def test_mid_filter_and_gnn(pipe, mid, nets):
     assert np.abs(q - r["gnn_scores"]).max() <= SCORE_TOL
 
 
-def test_mid_end_to_end(pipe, mid):
+def test_mid_end_to_end(pipe, mid, nets):
+    """trk_event equals the staged calls; the oracle's chain with the GPU's decision
+    taken only on margin edges gives identical labels (no fallback)."""
     ev, r = mid
-    labels, info = pipe.event(ev.x)
-    labels = labels.cpu().numpy()
-    margin = int(np.sum(np.abs(r["filter_scores"] - MU200.filter_cut) <= SCORE_TOL)) + \
-        int(np.sum(np.abs(r["gnn_scores"] - MU200.score_cut) <= SCORE_TOL))
-    print(f"mid event: n={ev.n} E_c={info['n_cand_edges']} E_f={info['n_filt_edges']} margin={margin}")
-    assert abs(info["n_cand_edges"] - r["src"].size) <= 2
-    if margin == 0 and info["n_cand_edges"] == r["src"].size:
-        assert np.array_equal(labels, r["labels"])
-    else:
-        hit, jac = label_agreement(labels, r["labels"])
-        assert hit >= 0.99
+    st = chain_parity(pipe, ev.x, nets, EMB_TOL, SCORE_TOL)
+    print(f"mid event: {st}")
+    assert abs(st["n_cand"] - r["src"].size) <= st["band_diffs"]
 
 
 # ---------------------------------------------------------------- pile-up 200
@@ -174,6 +170,18 @@ def test_full_batch_equals_alone(pipe, full):
         assert infos[b]["n_kept_edges"] == info["n_kept_edges"]
 
 
+@pytest.mark.timeout(900)
+def test_full_end_to_end(pipe, full, nets):
+    """The pile-up-200 event through trk_event against the whole FP64 oracle chain
+    (3M candidate edges, the filter on all of them, eight interaction-network
+    iterations on 1M edges), with the GPU's decision taken only on margin edges:
+    identical labels, every score within the FP32 tolerance."""
+    ev, _ = full
+    st = chain_parity(pipe, ev.x, nets, EMB_TOL, SCORE_TOL)
+    print(f"mu200 end to end: {st}")
+    assert 2_000_000 <= st["n_cand"] <= 5_000_000 and st["n_filt"] >= 500_000
+
+
 def test_full_deterministic(pipe, full):
     ev, _ = full
     a, ia = pipe.event(ev.x)
@@ -253,6 +261,29 @@ def test_fp8_matches_quantised_emulation(nets, mid):
     pf2 = pb.filter(e32, r["src"][sel], r["dst"][sel])[0].cpu().numpy()
     pb.close()
     assert np.array_equal(pf, pf2)
+
+
+def test_fp8_one_hidden_layer_matches_emulation(mid):
+    """The FP8 embedding with one hidden layer (3 -> 1024 -> 12): its activations are
+    requantised to E4M3 once, so there is no cascade of rounding flips through later
+    layers and the kernel is held to the bar that separates a rare activation on the
+    other side of an E4M3 boundary (a few outputs move) from a layout or scaling
+    mistake (every output moves): median <= 1e-4 and >= 98 % of outputs within 2e-3."""
+    from paper_2501_05520_amd.trk import Pipeline
+    from tests import quant_ref
+    ev, _ = mid
+    cfg1 = MU200.with_(emb_layers=1)
+    nets1 = make_weights(cfg1, 0)
+    rng = np.random.default_rng(6)
+    hits = np.sort(rng.choice(ev.n, 2048, replace=False))
+    pa = Pipeline(cfg1, nets1, "fp8all", max_hits=8192)
+    emb = pa.embed(ev.x[hits]).cpu().numpy()
+    pa.close()
+    eref = quant_ref.embed_fp8(ev.x[hits], nets1)
+    de = np.abs(emb - eref) / np.maximum(1.0, np.abs(eref))
+    print(f"fp8 one-hidden-layer embedding vs emulation: rel max {de.max():.3g} median {np.median(de):.3g} "
+          f"within 2e-3 {np.mean(de < 2e-3):.5f}")
+    assert np.median(de) <= 1e-4 and np.mean(de < 2e-3) >= 0.98 and de.max() < 0.1
 
 
 def test_bf16_with_fp32_embedding_keeps_the_fp32_graph(pipe, nets, mid):

@@ -51,6 +51,8 @@ def test_strerror():
     from paper_2501_05520_amd import trk
     assert trk.trk_strerror(0) == "ok"
     assert "capacity" in trk.trk_strerror(-3)
+    assert "deadline" in trk.trk_strerror(-7)
+    assert "shutting down" in trk.trk_strerror(-8)
     assert trk.trk_strerror(-99) == "unknown status"
 
 
