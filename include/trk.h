@@ -148,6 +148,26 @@ int trk_embed(trk_ctx* ctx, const float* d_x, int64_t n, float* d_emb, hipStream
 int trk_build_graph(trk_ctx* ctx, const float* d_emb, int64_t n, int32_t* d_src, int32_t* d_dst,
                     int64_t cap, int64_t* h_n_edges, int64_t* h_n_saturated, hipStream_t stream);
 
+/* Allocation-free radius graph, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes exactly what trk_build_graph computes, with the graph
+ * constants passed in instead of read from a context: emb_dim in [1, 16],
+ * radius > 0, k_max in [1, 1024].  It needs no context and calls no allocating
+ * routine: all of its scratch (35.2 MB) is one file-scope device array that
+ * each device holds for the life of the process; its device address is looked up
+ * on the first call on a device (the calling thread's current device, which
+ * d_emb, d_src, d_dst and the stream must belong to).
+ * Limits: n <= TRK_NOALLOC_MAX_HITS (else TRK_E_INVAL, nothing enqueued); at most
+ * min(cap, TRK_NOALLOC_MAX_EDGES) edges are written: a larger total returns
+ * TRK_E_CAPACITY with the total in *h_n_edges (as trk_build_graph does for cap).
+ * Synchronises the stream.  Calls that overlap on one device share the array and
+ * race: the caller serialises them (one stream, or its own ordering). */
+#define TRK_NOALLOC_MAX_HITS 131072
+#define TRK_NOALLOC_MAX_EDGES 4194304
+int trk_build_graph_noalloc(const float* d_emb, int64_t n, int32_t emb_dim, float radius, int32_t k_max,
+                            int32_t* d_src, int32_t* d_dst, int64_t cap, int64_t* h_n_edges,
+                            int64_t* h_n_saturated, hipStream_t stream);
+
 /* Edge filter (Section 2.2.2): p_f = sigmoid(MLP_f([emb_src, emb_dst])) for the m
  * edges (d_src, d_dst); writes d_scores[m] when non-NULL; copies the edges with
  * p_f > filter_cut, in input order, to d_kept_src/d_kept_dst and their count to

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtrk.so")
-SOURCES = ["scan", "cc", "mlp", "graph", "gnn", "trk_api", "serve", "train", "fit", "probe"]
+SOURCES = ["scan", "cc", "mlp", "graph", "graph_noalloc", "gnn", "trk_api", "serve", "train", "fit", "probe"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are disabled for every kernel

@@ -19,8 +19,8 @@ TRK_WEIGHTS_MAGIC = 0x5754524B
 TRK_FP32, TRK_BF16, TRK_FP8, TRK_FP8_ALL, TRK_BF16_EMB32, TRK_BF16X3, TRK_BF16X3_GNN_BF16 = range(7)
 STATUS = {0: "TRK_OK", -1: "TRK_E_INVAL", -2: "TRK_E_NOMEM", -3: "TRK_E_CAPACITY",
           -4: "TRK_E_DEVICE", -5: "TRK_E_WEIGHTS", -7: "TRK_E_EXPIRED", -8: "TRK_E_SHUTDOWN"}
-EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_filter", "trk_gnn",
-           "trk_components", "trk_event", "trk_batch", "trk_strerror",
+EXPORTS = ("trk_create", "trk_destroy", "trk_embed", "trk_build_graph", "trk_build_graph_noalloc", "trk_filter",
+           "trk_gnn", "trk_components", "trk_event", "trk_batch", "trk_strerror",
            "trk_server_create", "trk_server_submit", "trk_server_wait", "trk_server_stats",
            "trk_server_destroy", "trk_train_param_count", "trk_train_set_params", "trk_filter_train_fwd",
            "trk_filter_train_bwd", "trk_gnn_train_fwd", "trk_gnn_train_bwd", "trk_bce_with_logits",
@@ -93,6 +93,8 @@ def lib():
         L.trk_destroy.restype = None
         L.trk_embed.argtypes = [P, P, I64, P, P]
         L.trk_build_graph.argtypes = [P, P, I64, P, P, I64, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
+        L.trk_build_graph_noalloc.argtypes = [P, I64, I32, F, I32, P, P, I64, ctypes.POINTER(I64),
+                                              ctypes.POINTER(I64), P]
         L.trk_filter.argtypes = [P, P, I64, P, P, I64, P, P, P, I64, ctypes.POINTER(I64), P]
         L.trk_gnn.argtypes = [P, P, I64, P, P, I64, P, P]
         L.trk_components.argtypes = [P, I64, P, P, P, I64, F, P, P]
@@ -217,6 +219,19 @@ def trk_build_graph(ctx, emb, src, dst, stream=None):
     if rc == -3:
         raise TrkError(rc, f"trk_build_graph (needs {ne.value} edges)")
     _check(rc, "trk_build_graph")
+    return ne.value, ns.value
+
+
+def trk_build_graph_noalloc(emb, radius, k_max, src, dst, stream=None):
+    """Context-free, allocation-free radius graph on the current device; returns
+    (total edge count, saturated count)."""
+    ne, ns = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().trk_build_graph_noalloc(_ptr(emb), emb.shape[0], emb.shape[1] if emb.dim() == 2 else 0,
+                                       float(radius), int(k_max), _ptr(src), _ptr(dst), src.numel(),
+                                       ctypes.byref(ne), ctypes.byref(ns), _stream(stream))
+    if rc == -3:
+        raise TrkError(rc, f"trk_build_graph_noalloc (needs {ne.value} edges)")
+    _check(rc, "trk_build_graph_noalloc")
     return ne.value, ns.value
 
 
