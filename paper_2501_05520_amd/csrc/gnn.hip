@@ -9,7 +9,11 @@
 // per node by the node kernel (N x 2H) and gathered per edge, so each edge pays
 // for two H x H products instead of a 3H x H one.  Edge states e live in HBM in
 // the working precision and are rewritten in place each iteration; node states
-// stay FP32.  Aggregation is a gather, not a scatter: each node sums the states
+// stay FP32.  In FP8 the edge states and the per-node projections are stored as
+// E4M3 with per-tensor power-of-two scales (GnnScale) and the edge-side products
+// (the e-block and the second layer of phi_e, the e-block of phi_o) run on FP8
+// matrix cores; the node side (encoders, phi_v, the projections) runs in BF16.
+// Aggregation is a gather, not a scatter: each node sums the states
 // of its incident edges through CSR (by source) and CSC (by destination) index
 // lists sorted by edge id, in a fixed order, so the sums are deterministic and an
 // event gives the same scores alone or batched with others.
@@ -55,6 +59,24 @@ __device__ __forceinline__ void load4<PrecX3>(const x3_t* p, float& a, float& b,
   a = v[0]; b = v[1]; c = v[2]; d = v[3];
 }
 
+template <>
+__device__ __forceinline__ void load4<PrecFP8>(const uint8_t* p, float& a, float& b, float& c, float& d) {
+  const int v = *(const int*)p;
+  const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(v, false);
+  const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(v, true);
+  a = lo[0]; b = lo[1]; c = hi[0]; d = hi[1];
+}
+
+template <class P>
+constexpr bool is_fp8() { return std::is_same<P, PrecFP8>::value; }
+
+// an edge state or node projection as stored: E4M3(v * s) in FP8, v itself otherwise
+template <class P>
+__device__ __forceinline__ void store_state4(typename P::act_t* p, float a, float b, float c, float d, float s) {
+  if constexpr (is_fp8<P>()) P::store4_scaled(p, a, b, c, d, s);
+  else P::store4(p, a, b, c, d);
+}
+
 // copy rows [row0, row0 + MT) of a [rows][H] act array into LDS (zero past `rows`):
 // every load of the tile is requested before the first LDS write
 template <class P, int H, int MT, int NT>
@@ -91,11 +113,12 @@ __device__ __forceinline__ void gemm_k(f32x4 (&acc)[MTW][NTW], const typename P:
 
 // ---------------------------------------------------------------------------
 // node encoder: h0 = tanh(tanh(x W1 + b1) W2 + b2); proj = h0 [W_a | W_b]
+// (products in P, projections stored in Q's format with scale ps)
 // ---------------------------------------------------------------------------
-template <class P, int H, int MT, int NW>
+template <class P, class Q, int H, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __restrict__ x, int n, DevLayer l1,
                                                               DevLayer l2, DevLayer lp, float* __restrict__ h,
-                                                              typename P::act_t* __restrict__ proj) {
+                                                              typename Q::act_t* __restrict__ proj, float ps) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
   __shared__ __align__(16) T xin[MT * S::LDI];
@@ -150,8 +173,8 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
       for (int i = 0; i < S::MTW; ++i) {
         const int m = i * 16 + r;
         if (row0 + m < n)
-          P::store4(proj + (size_t)(row0 + m) * 2 * H + nn, accp[i][j][0], accp[i][j][1], accp[i][j][2],
-                    accp[i][j][3]);
+          store_state4<Q>(proj + (size_t)(row0 + m) * 2 * H + nn, accp[i][j][0], accp[i][j][1], accp[i][j][2],
+                          accp[i][j][3], ps);
       }
     }
     __syncthreads();
@@ -160,12 +183,13 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
 
 // ---------------------------------------------------------------------------
 // edge encoder: e0 = tanh(tanh([x_s, x_t] W1 + b1) W2 + b2)
+// (products in P, states stored in Q's format with scale se)
 // ---------------------------------------------------------------------------
-template <class P, int H, int MT, int NW>
+template <class P, class Q, int H, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __restrict__ x, int n,
                                                               const int* __restrict__ src, const int* __restrict__ dst,
                                                               int64_t m_cap, const int* d_m, DevLayer l1, DevLayer l2,
-                                                              typename P::act_t* __restrict__ e, int* d_err) {
+                                                              typename Q::act_t* __restrict__ e, int* d_err, float se) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
   __shared__ __align__(16) T xin[MT * S::LDI];
@@ -215,8 +239,10 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
       for (int i = 0; i < S::MTW; ++i) {
         const int64_t row = row0 + i * 16 + r;
         if (row < m)
-          P::store4(e + (size_t)row * H + nn, trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x)), trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y)),
-                    trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z)), trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w)));
+          store_state4<Q>(e + (size_t)row * H + nn, trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x)),
+                          trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y)),
+                          trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z)),
+                          trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w)), se);
       }
     }
     __syncthreads();
@@ -235,7 +261,7 @@ __global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* _
                                                        const typename P::act_t* __restrict__ proj,
                                                        const int* __restrict__ src, const int* __restrict__ dst,
                                                        int n, int64_t m_cap, const int* d_m, DevLayer lc, DevLayer l2,
-                                                       DevVec lo, float* __restrict__ scores) {
+                                                       DevVec lo, GnnScale sc, float* __restrict__ scores) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
   constexpr int LDP = H + 4;                       // fp32 row stride of the gathered tile
@@ -249,6 +275,10 @@ __global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* _
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
   const int64_t ntiles = (m + MT - 1) / MT;
+  // product scales of the two layers, folded with the 2 log2(e) of the tanh epilogue
+  // (the layers' dq is 1 unless FP8: the constant itself there)
+  const float s1 = is_fp8<P>() ? lc.dq * TRK_2LOG2E : TRK_2LOG2E;
+  const float s2 = is_fp8<P>() ? l2.dq * TRK_2LOG2E : TRK_2LOG2E;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
     {
@@ -290,6 +320,13 @@ __global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* _
           float pa[V], pb[V];
           P::unpack16(ua[it], pa);
           P::unpack16(ub[it], pb);
+          if constexpr (is_fp8<P>()) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              pa[q] *= sc.inv_p;
+              pb[q] *= sc.inv_p;
+            }
+          }
 #pragma unroll
           for (int q = 0; q < V; q += 4) {
             // kept times 2 log2(e), the form the tanh epilogue consumes
@@ -318,10 +355,10 @@ __global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* _
       for (int i = 0; i < S::MTW; ++i) {
         const int mm = i * 16 + r;
         const float4 pv = *(const float4*)(pre + mm * LDP + nn);
-        const float v0 = trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, pv.x));
-        const float v1 = trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, pv.y));
-        const float v2 = trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, pv.z));
-        const float v3 = trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, pv.w));
+        const float v0 = trk_tanh_log2(fmaf(acc[i][j][0], s1, pv.x));
+        const float v1 = trk_tanh_log2(fmaf(acc[i][j][1], s1, pv.y));
+        const float v2 = trk_tanh_log2(fmaf(acc[i][j][2], s1, pv.z));
+        const float v3 = trk_tanh_log2(fmaf(acc[i][j][3], s1, pv.w));
         if (OUT) part[i] += v0 * w2.x + v1 * w2.y + v2 * w2.z + v3 * w2.w;
         acc[i][j] = f32x4{v0, v1, v2, v3};
       }
@@ -361,9 +398,14 @@ __global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* _
           const int64_t row = row0 + mm;
           float e0, e1, e2, e3;
           load4<P>(et + mm * S::LDH + nn, e0, e1, e2, e3);
+          if constexpr (is_fp8<P>()) {
+            e0 *= sc.inv_e; e1 *= sc.inv_e; e2 *= sc.inv_e; e3 *= sc.inv_e;
+          }
           if (row < m)
-            P::store4(e + (size_t)row * H + nn, e0 + trk_tanh_log2(fmaf(acc[i][j][0], TRK_2LOG2E, b.x)), e1 + trk_tanh_log2(fmaf(acc[i][j][1], TRK_2LOG2E, b.y)),
-                      e2 + trk_tanh_log2(fmaf(acc[i][j][2], TRK_2LOG2E, b.z)), e3 + trk_tanh_log2(fmaf(acc[i][j][3], TRK_2LOG2E, b.w)));
+            store_state4<P>(e + (size_t)row * H + nn, e0 + trk_tanh_log2(fmaf(acc[i][j][0], s2, b.x)),
+                            e1 + trk_tanh_log2(fmaf(acc[i][j][1], s2, b.y)),
+                            e2 + trk_tanh_log2(fmaf(acc[i][j][2], s2, b.z)),
+                            e3 + trk_tanh_log2(fmaf(acc[i][j][3], s2, b.w)), sc.e);
         }
       }
       __syncthreads();
@@ -384,7 +426,7 @@ template <class P, int H>
 __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t* __restrict__ e,
                                                         const int* __restrict__ sptr, const int* __restrict__ sidx,
                                                         const int* __restrict__ dptr, const int* __restrict__ didx,
-                                                        int n, float* __restrict__ msg) {
+                                                        int n, float* __restrict__ msg, float inv_e) {
   typedef typename P::act_t T;
   constexpr int V = 16 / (int)sizeof(T);   // columns per lane per row
   constexpr int LPR = H / V;               // lanes per row
@@ -422,6 +464,10 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
         if (k < cnt) {
           float v[V];
           P::unpack16(*(const uint4*)(e + (size_t)eid * H + col), v);
+          if constexpr (is_fp8<P>()) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) v[q] *= inv_e;
+          }
 #pragma unroll
           for (int q = 0; q < V; ++q) acc[q] += v[q];
         }
@@ -444,11 +490,12 @@ __global__ __launch_bounds__(256) void aggregate_kernel(const typename P::act_t*
 // ---------------------------------------------------------------------------
 // node step: h <- h + tanh(tanh([h, m] W1 + b1) W2 + b2) with m the aggregated
 // messages; proj = h [W_a | W_b] for the next edge step (or the output head)
+// (products in P, projections stored in Q's format with scale ps)
 // ---------------------------------------------------------------------------
-template <class P, int H, int MT, int NW>
+template <class P, class Q, int H, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ h, const float* __restrict__ msg,
                                                             int n, DevLayer l1, DevLayer l2, DevLayer lp,
-                                                            typename P::act_t* __restrict__ proj) {
+                                                            typename Q::act_t* __restrict__ proj, float ps) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
   __shared__ __align__(16) T in[MT * S::LD2];
@@ -524,7 +571,8 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
       for (int i = 0; i < S::MTW; ++i) {
         const int node = row0 + i * 16 + r;
         if (node < n)
-          P::store4(proj + (size_t)node * 2 * H + nn, accp[i][j][0], accp[i][j][1], accp[i][j][2], accp[i][j][3]);
+          store_state4<Q>(proj + (size_t)node * 2 * H + nn, accp[i][j][0], accp[i][j][1], accp[i][j][2],
+                          accp[i][j][3], ps);
       }
     }
     __syncthreads();
@@ -572,45 +620,55 @@ __global__ void incidence_fill(const int* __restrict__ key, int64_t m_cap, const
 // finish early are replaced at once, which balances uneven degrees).
 int agg_blocks(int n) { return blocks_for(n, 4, 65536); }
 
-// the unrolled products read ceil(K / KB) fragment blocks per n-tile of each layer
-template <class P, int H>
+// the unrolled products read ceil(K / KB) fragment blocks per n-tile of each layer:
+// the edge-side layers in P, the node side (encoders, node network, projections) in N
+template <class P, class N, int H>
 bool gnn_shapes_ok(const DevGNN& net) {
-  auto nkb = [](int K) { return (K + P::KB - 1) / P::KB; };
-  const DevLayer* sq[] = {&net.node_enc2, &net.edge_enc2, &net.edge_c, &net.edge_ab, &net.edge_2, &net.node_2,
-                          &net.out_c, &net.out_ab};
-  for (const DevLayer* L : sq)
-    if (L->nkb != nkb(H)) return false;
-  return net.H == H && net.node_enc1.nkb == nkb(3) && net.edge_enc1.nkb == nkb(6) && net.node_1.nkb == nkb(2 * H);
+  auto nkb = [](int K, int KB) { return (K + KB - 1) / KB; };
+  const DevLayer* edge_side[] = {&net.edge_c, &net.edge_2, &net.out_c};
+  const DevLayer* node_side[] = {&net.node_enc2, &net.edge_enc2, &net.edge_ab, &net.node_2, &net.out_ab};
+  for (const DevLayer* L : edge_side)
+    if (L->nkb != nkb(H, P::KB)) return false;
+  for (const DevLayer* L : node_side)
+    if (L->nkb != nkb(H, N::KB)) return false;
+  return net.H == H && net.node_enc1.nkb == nkb(3, N::KB) && net.edge_enc1.nkb == nkb(6, N::KB) &&
+         net.node_1.nkb == nkb(2 * H, N::KB);
 }
 
-template <class P, int H, int MTE, int MTN, int NW, int EWPE = NW / 4>
+// P: precision of the edge-side products and of the stored edge states and
+// projections; N: precision of the node-side products (N = P except in FP8)
+template <class P, class N, int H, int MTE, int MTN, int NW, int EWPE = NW / 4>
 void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap, const int* d_m,
              float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool src_sorted) {
   typedef typename P::act_t T;
   T* proj = (T*)g.proj;
   T* e = (T*)g.e;
+  const GnnScale sc = net.sc;
   launch_incidence(src, dst, m_cap, d_m, n, g, s, src_sorted);
   const int ngrid = (int)std::min<int64_t>((n + MTN - 1) / MTN, (int64_t)n_cu * 8);
   const int64_t etiles = (m_cap + MTE - 1) / MTE;
   const int egrid = (int)std::min<int64_t>(etiles, (int64_t)n_cu * 8);
   const DevLayer& first_proj = net.iters > 0 ? net.edge_ab : net.out_ab;
   if (ngrid > 0)
-    node_encode_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(x, n, net.node_enc1, net.node_enc2, first_proj, g.h, proj);
+    node_encode_kernel<N, P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(x, n, net.node_enc1, net.node_enc2, first_proj,
+                                                                   g.h, proj, sc.p);
   if (egrid > 0)
-    edge_encode_kernel<P, H, MTE, NW><<<egrid, NW * 64, 0, s>>>(x, n, src, dst, m_cap, d_m, net.edge_enc1,
-                                                                net.edge_enc2, e, d_err);
+    edge_encode_kernel<N, P, H, MTE, NW><<<egrid, NW * 64, 0, s>>>(x, n, src, dst, m_cap, d_m, net.edge_enc1,
+                                                                   net.edge_enc2, e, d_err, sc.e);
   for (int it = 0; it < net.iters; ++it) {
     if (egrid > 0)
       edge_kernel<P, H, MTE, NW, false, EWPE><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.edge_c,
-                                                                  net.edge_2, net.out_2, nullptr);
+                                                                  net.edge_2, net.out_2, sc, nullptr);
     const DevLayer& lp = it + 1 < net.iters ? net.edge_ab : net.out_ab;
-    aggregate_kernel<P, H><<<agg_blocks(n), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg);
+    aggregate_kernel<P, H><<<agg_blocks(n), 256, 0, s>>>(e, g.rowptr, g.rowidx, g.cscptr, g.cscidx, n, g.msg,
+                                                         sc.inv_e);
     if (ngrid > 0)
-      node_step_kernel<P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj);
+      node_step_kernel<N, P, H, MTN, NW><<<ngrid, NW * 64, 0, s>>>(g.h, g.msg, n, net.node_1, net.node_2, lp, proj,
+                                                                   sc.p);
   }
   if (egrid > 0)
     edge_kernel<P, H, MTE, NW, true, EWPE><<<egrid, NW * 64, 0, s>>>(e, proj, src, dst, n, m_cap, d_m, net.out_c,
-                                                               net.edge_2, net.out_2, scores);
+                                                               net.edge_2, net.out_2, sc, scores);
 }
 
 // Row tiles of the H=128 kernels: 64-edge tiles on eight waves with the edge kernel's
@@ -620,10 +678,12 @@ void run_gnn(const DevGNN& net, const float* x, int n, const int* src, const int
 template <class P>
 void run_gnn128(const DevGNN& net, const float* x, int n, const int* src, const int* dst, int64_t m_cap,
                 const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool sorted) {
-  if (std::is_same<P, PrecX3>::value)
-    run_gnn<P, 128, 64, 32, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
+  if constexpr (std::is_same<P, PrecX3>::value)
+    run_gnn<P, P, 128, 64, 32, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
+  else if constexpr (std::is_same<P, PrecFP8>::value)
+    run_gnn<P, PrecBF16, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
   else
-    run_gnn<P, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
+    run_gnn<P, P, 128, 64, 64, 8, 4>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, sorted);
 }
 
 }  // namespace
@@ -655,19 +715,27 @@ int launch_gnn(int prec, const DevGNN& net, const float* x, int n, const int* sr
                const int* d_m, float* scores, GnnScratch& g, int n_cu, int* d_err, hipStream_t s, bool src_sorted) {
   if (n <= 0) return 0;
   const bool f32 = prec == TRK_PREC_F32;
-  // split BF16 stores the same fragment blocks per k block as BF16
-  const bool ok = net.H == 128 ? (f32 ? gnn_shapes_ok<PrecF32, 128>(net) : gnn_shapes_ok<PrecBF16, 128>(net))
-                               : (f32 ? gnn_shapes_ok<PrecF32, 32>(net) : gnn_shapes_ok<PrecBF16, 32>(net));
+  // split BF16 stores the same fragment blocks per k block as BF16; FP8 runs its
+  // node side in BF16 and exists for H = 128 only (k in blocks of 128)
+  if (prec == TRK_PREC_FP8) {
+    if (net.H != 128 || !gnn_shapes_ok<PrecFP8, PrecBF16, 128>(net)) return -1;
+    run_gnn128<PrecFP8>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted);
+    return 0;
+  }
+  const bool ok = net.H == 128 ? (f32 ? gnn_shapes_ok<PrecF32, PrecF32, 128>(net)
+                                      : gnn_shapes_ok<PrecBF16, PrecBF16, 128>(net))
+                               : (f32 ? gnn_shapes_ok<PrecF32, PrecF32, 32>(net)
+                                      : gnn_shapes_ok<PrecBF16, PrecBF16, 32>(net));
   if (!ok) return -1;
   if (prec == TRK_PREC_X3) {
     if (net.H == 128) { run_gnn128<PrecX3>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
-    if (net.H == 32) { run_gnn<PrecX3, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+    if (net.H == 32) { run_gnn<PrecX3, PrecX3, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
   } else if (prec == TRK_PREC_F32) {
     if (net.H == 128) { run_gnn128<PrecF32>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
-    if (net.H == 32) { run_gnn<PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+    if (net.H == 32) { run_gnn<PrecF32, PrecF32, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
   } else {
     if (net.H == 128) { run_gnn128<PrecBF16>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
-    if (net.H == 32) { run_gnn<PrecBF16, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
+    if (net.H == 32) { run_gnn<PrecBF16, PrecBF16, 32, 64, 64, 1>(net, x, n, src, dst, m_cap, d_m, scores, g, n_cu, d_err, s, src_sorted); return 0; }
   }
   return -1;
 }

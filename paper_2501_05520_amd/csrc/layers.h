@@ -20,9 +20,19 @@ struct DevVec {
   float b = 0.f;
 };
 
+// Storage scales of the interaction network's edge states and node projections.
+// FP8 keeps each as E4M3(value * scale) with a per-tensor power-of-two scale chosen
+// on the host from a bound on the tensor (so nothing saturates); every other
+// precision stores the values themselves (scales 1).
+struct GnnScale {
+  float e = 1.f, inv_e = 1.f;    // edge states
+  float p = 1.f, inv_p = 1.f;    // per-node projections
+};
+
 // The interaction network split for the factorised edge updates.
 struct DevGNN {
   int H = 0, iters = 0;
+  GnnScale sc;
   DevLayer node_enc1, node_enc2;   // [3,H], [H,H]
   DevLayer edge_enc1, edge_enc2;   // [6,H], [H,H]
   DevLayer edge_c;                 // e-block of the first edge-network layer [H,H] (+ its bias)

@@ -180,6 +180,26 @@ struct PrecFP8 {
     v = __builtin_amdgcn_cvt_pk_fp8_f32(c * ACT_SCALE, d * ACT_SCALE, v, true);
     *(int*)p = v;
   }
+  // four E4M3 values of (s * a, s * b, s * c, s * d), element k at byte k
+  static __device__ __forceinline__ void store4_scaled(uint8_t* p, float a, float b, float c, float d, float s) {
+    int v = __builtin_amdgcn_cvt_pk_fp8_f32(a * s, b * s, 0, false);
+    v = __builtin_amdgcn_cvt_pk_fp8_f32(c * s, d * s, v, true);
+    *(int*)p = v;
+  }
+  // the sixteen E4M3 values held by 16 bytes of a row, as stored (scale not removed)
+  static constexpr int V16 = 16;
+  static __device__ __forceinline__ void unpack16(const uint4& u, float (&v)[V16]) {
+    const int w[4] = {(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w[q], false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w[q], true);
+      v[4 * q] = lo[0];
+      v[4 * q + 1] = lo[1];
+      v[4 * q + 2] = hi[0];
+      v[4 * q + 3] = hi[1];
+    }
+  }
 };
 
 template <class P>

@@ -109,7 +109,8 @@ int validate_config(const trk_config* c) {
   if (!width_ok(c->gnn_hidden, {32, 128}) || c->gnn_iters < 0 || c->gnn_iters > 64) return TRK_E_INVAL;
   if (!(c->radius > 0.f) || c->k_max < 1 || c->k_max > 1024) return TRK_E_INVAL;
   if (c->precision < TRK_FP32 || c->precision > TRK_BF16X3_GNN_BF16) return TRK_E_INVAL;
-  if ((c->precision == TRK_FP8 || c->precision == TRK_FP8_ALL) && (c->emb_hidden % 128 || c->filt_hidden % 128))
+  if ((c->precision == TRK_FP8 || c->precision == TRK_FP8_ALL) &&
+      (c->emb_hidden % 128 || c->filt_hidden % 128 || c->gnn_hidden != 128))
     return TRK_E_INVAL;
   if (c->max_hits < 1 || c->max_hits > (1LL << 30)) return TRK_E_INVAL;
   if (c->max_cand_edges < 1 || c->max_cand_edges > (1LL << 31) - 1) return TRK_E_INVAL;
@@ -175,12 +176,13 @@ struct WeightUpload {
     memcpy(bytes.data() + off, src, n);
     return off;
   }
-  void layer(DevLayer& D, const HostLinear& L, int prec) {
+  // act_scale: the storage scale of the FP8 activations the layer reads
+  void layer(DevLayer& D, const HostLinear& L, int prec, float act_scale = FP8_ACT_SCALE) {
     D.K = L.K;
     D.N = L.N;
     const float scale = prec == TRK_PREC_FP8 ? fp8_weight_scale(L.w.data(), L.w.size()) : 1.f;
-    // an FP8 layer reads FP8 activations (stored times FP8_ACT_SCALE) and FP8 weights
-    D.dq = prec == TRK_PREC_FP8 ? 1.f / (scale * FP8_ACT_SCALE) : 1.f;
+    // an FP8 layer reads FP8 activations (stored times act_scale) and FP8 weights
+    D.dq = prec == TRK_PREC_FP8 ? 1.f / (scale * act_scale) : 1.f;
     std::vector<uint8_t> f = make_fragments(L.w.data(), L.K, L.N, prec, D.nkb, D.nnt, scale);
     std::vector<float> b((size_t)D.nnt * 16, 0.f), bs((size_t)D.nnt * 16, 0.f);
     for (int n = 0; n < L.N; ++n) {
@@ -208,6 +210,32 @@ struct WeightUpload {
     for (auto& v : vfixes) v.V->w = (const float*)((char*)base + v.wofs);
   }
 };
+
+// Scales of the FP8 interaction network's stored tensors.  Every update adds a tanh
+// to a tanh-initialised state, so |e|, |h| < T + 1 after T iterations; a projection
+// column c of h W is then bounded by (T + 1) sum_k |W[k][c]| (with 1 % for the BF16
+// roundings of h and W).  Each scale is the largest power of two that keeps its
+// bound inside E4M3's 448, so no stored value saturates.
+float pow2_scale_for(double bound) {
+  return bound > 0 ? std::ldexp(1.f, (int)std::floor(std::log2(448.0 / bound))) : 1.f;
+}
+
+GnnScale gnn_state_scales(int iters, const HostLinear& eab, const HostLinear& oab) {
+  const double hb = (double)(iters + 1);
+  double colmax = 0;
+  for (const HostLinear* L : {&eab, &oab})
+    for (int n = 0; n < L->N; ++n) {
+      double s = 0;
+      for (int kk = 0; kk < L->K; ++kk) s += std::fabs((double)L->w[(size_t)kk * L->N + n]);
+      colmax = std::max(colmax, s);
+    }
+  GnnScale sc;
+  sc.e = pow2_scale_for(hb);
+  sc.p = pow2_scale_for(hb * colmax * 1.01);
+  sc.inv_e = 1.f / sc.e;
+  sc.inv_p = 1.f / sc.p;
+  return sc;
+}
 
 int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   const trk_config& k = c->cfg;
@@ -252,17 +280,24 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   DevGNN& g = c->gnn;
   g.H = H;
   g.iters = k.gnn_iters;
-  up.layer(g.node_enc1, ne1, prec_gnn);
-  up.layer(g.node_enc2, ne2, prec_gnn);
-  up.layer(g.edge_enc1, ee1, prec_gnn);
-  up.layer(g.edge_enc2, ee2, prec_gnn);
-  up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec_gnn);
-  up.layer(g.edge_ab, side_by_side(en1, 0, H, H), prec_gnn);
+  // FP8 interaction network: the edge-side layers (e-blocks of phi_e and phi_o, the
+  // second layer of phi_e) in FP8, the node side in BF16; edge states and projections
+  // stored as E4M3 with power-of-two scales from bounds (see gnn_state_scales)
+  const bool gnn8 = prec_gnn == TRK_PREC_FP8;
+  const int pn = gnn8 ? TRK_PREC_BF16 : prec_gnn;
+  const HostLinear eab = side_by_side(en1, 0, H, H), oab = side_by_side(o1, 0, H, H);
+  g.sc = gnn8 ? gnn_state_scales(k.gnn_iters, eab, oab) : GnnScale{};
+  up.layer(g.node_enc1, ne1, pn);
+  up.layer(g.node_enc2, ne2, pn);
+  up.layer(g.edge_enc1, ee1, pn);
+  up.layer(g.edge_enc2, ee2, pn);
+  up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec_gnn, g.sc.e);
+  up.layer(g.edge_ab, eab, pn);
   up.layer(g.edge_2, en2, prec_gnn);
-  up.layer(g.node_1, nn1, prec_gnn);
-  up.layer(g.node_2, nn2, prec_gnn);
-  up.layer(g.out_c, rows_of(o1, 2 * H, H, true), prec_gnn);
-  up.layer(g.out_ab, side_by_side(o1, 0, H, H), prec_gnn);
+  up.layer(g.node_1, nn1, pn);
+  up.layer(g.node_2, nn2, pn);
+  up.layer(g.out_c, rows_of(o1, 2 * H, H, true), prec_gnn, g.sc.e);
+  up.layer(g.out_ab, oab, pn);
   up.vec(g.out_2, o2);
   if (hipMalloc(&c->wmem, up.bytes.size()) != hipSuccess) return TRK_E_NOMEM;
   if (hipMemcpy(c->wmem, up.bytes.data(), up.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return TRK_E_DEVICE;
@@ -280,7 +315,7 @@ int alloc_scratch(trk_ctx* c) {
   const trk_config& k = c->cfg;
   const int64_t NH = k.max_hits, CC = k.max_cand_edges, CF = k.max_kept_edges;
   const int H = k.gnn_hidden;
-  const size_t act = (c->prec_gnn == TRK_PREC_F32 || c->prec_gnn == TRK_PREC_X3) ? 4 : 2;
+  const size_t act = (c->prec_gnn == TRK_PREC_F32 || c->prec_gnn == TRK_PREC_X3) ? 4 : c->prec_gnn == TRK_PREC_FP8 ? 1 : 2;
   Arena& a = c->arena;
   GraphScratch& g = c->graph;
   GnnScratch& s = c->gs;
@@ -447,8 +482,8 @@ int trk_create(const trk_config* cfg, const void* h_weights, size_t nbytes, int 
   switch (cfg->precision) {
     // (embedding, filter, interaction network)
     case TRK_BF16: c->prec_emb = c->prec = c->prec_gnn = TRK_PREC_BF16; break;
-    case TRK_FP8: c->prec_emb = TRK_PREC_BF16; c->prec = TRK_PREC_FP8; c->prec_gnn = TRK_PREC_BF16; break;
-    case TRK_FP8_ALL: c->prec_emb = c->prec = TRK_PREC_FP8; c->prec_gnn = TRK_PREC_BF16; break;
+    case TRK_FP8: c->prec_emb = TRK_PREC_BF16; c->prec = c->prec_gnn = TRK_PREC_FP8; break;
+    case TRK_FP8_ALL: c->prec_emb = c->prec = c->prec_gnn = TRK_PREC_FP8; break;
     case TRK_BF16_EMB32: c->prec_emb = TRK_PREC_F32; c->prec = c->prec_gnn = TRK_PREC_BF16; break;
     case TRK_BF16X3: c->prec_emb = c->prec = c->prec_gnn = TRK_PREC_X3; break;
     case TRK_BF16X3_GNN_BF16: c->prec_emb = c->prec = TRK_PREC_X3; c->prec_gnn = TRK_PREC_BF16; break;

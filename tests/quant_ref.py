@@ -63,3 +63,70 @@ def filter_fp8(emb, src, dst, nets):
     w, b = layers[-1]
     z = h @ np.asarray(w, np.float64) + np.asarray(b, np.float64)
     return 1.0 / (1.0 + np.exp(-z[:, 0]))
+
+
+# ---------------------------------------------------------------------------
+# FP8 interaction network: edge states and per-node projections stored as
+# E4M3(v * s) with power-of-two scales from bounds, the edge-side products (e-block
+# and second layer of the edge network, e-block of the output head) in FP8 with
+# activations E4M3(256 tanh), the node side (encoders, node network, projections)
+# in BF16, FP32 node states and message sums.
+# ---------------------------------------------------------------------------
+def pow2_for_bound(bound):
+    return 2.0 ** math.floor(math.log2(448.0 / bound)) if bound > 0 else 1.0
+
+
+def gnn_state_scales(nets, iters):
+    H = nets["node_enc"][1][0].shape[1]
+    hb = float(iters + 1)
+    colmax = 0.0
+    for name in ("edge_net", "out"):
+        w = np.asarray(nets[name][0][0], np.float64)
+        colmax = max(colmax, np.abs(w[:H]).sum(axis=0).max(), np.abs(w[H:2 * H]).sum(axis=0).max())
+    return pow2_for_bound(hb), pow2_for_bound(hb * colmax * 1.01)
+
+
+def _q(v, s):
+    return e4m3(np.asarray(v, np.float64) * s) / s
+
+
+def _fp8_w(w):
+    s = pow2_scale(w)
+    return e4m3(np.asarray(w, np.float64) * s) / s
+
+
+def gnn_fp8(x, src, dst, nets, iters):
+    x = np.asarray(x, np.float32)
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    H = nets["node_enc"][1][0].shape[1]
+    se, sp = gnn_state_scales(nets, iters)
+    (n1w, n1b), (n2w, n2b) = nets["node_enc"]
+    (e1w, e1b), (e2w, e2b) = nets["edge_enc"]
+    (ew1, eb1), (ew2, eb2) = nets["edge_net"]
+    (vw1, vb1), (vw2, vb2) = nets["node_net"]
+    (ow1, ob1), (ow2, ob2) = nets["out"]
+    f64 = lambda a: np.asarray(a, np.float64)
+
+    def proj(h, w1):                        # [h W_a | h W_b] in BF16, stored as E4M3
+        return _q(bf16(h) @ bf16(np.concatenate([w1[:H], w1[H:2 * H]], axis=1)), sp)
+
+    h = np.tanh(bf16(np.tanh(_bf16_layer(x, n1w, n1b))) @ bf16(n2w) + f64(n2b))
+    pj = proj(h, ew1 if iters > 0 else ow1)
+    u = np.concatenate([x[src], x[dst]], axis=1)
+    e = _q(np.tanh(bf16(np.tanh(_bf16_layer(u, e1w, e1b))) @ bf16(e2w) + f64(e2b)), se)
+    wc, w2, woc = _fp8_w(ew1[2 * H:]), _fp8_w(ew2), _fp8_w(ow1[2 * H:])
+    n = x.shape[0]
+    for it in range(iters):
+        t1 = np.tanh(e @ wc + pj[src, :H] + pj[dst, H:] + f64(eb1))
+        t1 = e4m3(256.0 * t1) / 256.0
+        e = _q(e + np.tanh(t1 @ w2 + f64(eb2)), se)
+        m = np.zeros((n, H))
+        np.add.at(m, src, e)
+        np.add.at(m, dst, e)
+        t = np.tanh(np.concatenate([bf16(h), bf16(m)], axis=1) @ bf16(vw1) + f64(vb1))
+        h = h + np.tanh(bf16(t) @ bf16(vw2) + f64(vb2))
+        pj = proj(h, ew1 if it + 1 < iters else ow1)
+    v = np.tanh(e @ woc + pj[src, :H] + pj[dst, H:] + f64(ob1))
+    z = v @ f64(ow2)[:, 0] + float(ob2[0])
+    return 1.0 / (1.0 + np.exp(-z))

@@ -46,7 +46,7 @@ def test_tiny_mix_equals_alone():
     assert st["completed"] == len(xs) and st["batches"] < len(xs)
 
 
-@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3", "fp8"])
 def test_mu_mix_equals_alone(precision):
     from paper_2501_05520_amd.trk import Server, Pipeline
     nets = make_weights(MU200, 0)
