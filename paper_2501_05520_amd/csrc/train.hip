@@ -14,9 +14,13 @@
 // Precision: an FP32 context trains with FP32 products; a BF16 context (the
 // training configuration with BF16 activations) rounds the operands of every
 // product - activations, deltas and the weight copies - to BF16 on the way into
-// the matrix cores (v_mfma_f32_16x16x32_bf16) and accumulates in FP32; the master
-// parameters, the Adam moments, stored activations and the element-wise steps stay
-// FP32.
+// the matrix cores (v_mfma_f32_16x16x32_bf16) and accumulates in FP32, and keeps
+// the activations that the forward pass stores for the backward (the filter's
+// hidden layers, the encoders' hidden layers, the per-iteration states h^t and e^t,
+// the output head's hidden layer, the embedding's hidden layers) in BF16, which
+// halves that memory; the forward pass continues from the stored BF16 values, so
+// forward and backward see the same numbers.  The master parameters, the Adam
+// moments, the deltas and the element-wise arithmetic stay FP32.
 //
 // Building blocks, all on MFMA (v_mfma_f32_16x16x4_f32 or the BF16 form) or plain
 // vector code:
@@ -38,6 +42,31 @@
 namespace {
 
 enum { EPI_STORE = 0, EPI_ACC = 1, EPI_BIAS = 2, EPI_BIAS_TANH = 3, EPI_DTANH = 4 };
+
+}  // namespace
+
+// A buffer of activations kept by a forward pass for its backward: FP32, or BF16
+// in a BF16 context.  Transient FP32 buffers convert to it implicitly.
+struct ActBuf {
+  void* p = nullptr;
+  int bf16 = 0;
+  ActBuf() = default;
+  ActBuf(std::nullptr_t) {}
+  ActBuf(float* q) : p(q) {}
+  ActBuf(const float* q) : p((void*)q) {}
+  ActBuf(void* q, int b) : p(q), bf16(b) {}
+  __device__ __forceinline__ float get(size_t i) const {
+    return bf16 ? (float)((const __bf16*)p)[i] : ((const float*)p)[i];
+  }
+  __device__ __forceinline__ void set(size_t i, float v) const {
+    if (bf16) ((__bf16*)p)[i] = (__bf16)v;
+    else ((float*)p)[i] = v;
+  }
+  // the buffer from element `off` on
+  ActBuf at(size_t off) const { return ActBuf((char*)p + off * (bf16 ? 2 : 4), bf16); }
+};
+
+namespace {
 
 // node index clamped into [0, n): an out-of-range edge end reads node 0 instead of
 // memory past the node arrays (the inference entry points report such edges)
@@ -102,9 +131,9 @@ __global__ void bias_fill_kernel(float* out, float* out_s, int nout, const float
 constexpr int RG_NW = 4;
 
 template <class P, int NTW, int RG_MT, int RG_KMAX>
-__global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __restrict__ X, int ldx, int K, int64_t m,
-                                                             DevLayer W, float* __restrict__ out, int ldo, int N,
-                                                             int epi, const float* __restrict__ aux, int ldaux) {
+__global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int K, int64_t m, DevLayer W,
+                                                             ActBuf out, int ldo, int N, int epi, ActBuf aux,
+                                                             int ldaux) {
   typedef typename P::act_t T;
   constexpr int LDX = RG_KMAX + P::PAD;
   constexpr int MTW = RG_MT / 16;
@@ -116,7 +145,7 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __rest
     const int64_t row0 = t * RG_MT;
     for (int idx = threadIdx.x; idx < RG_MT * kpad; idx += blockDim.x) {
       const int mm = idx / kpad, k = idx - mm * kpad;
-      xs[mm * LDX + k] = P::cvt((row0 + mm < m && k < K) ? X[(size_t)(row0 + mm) * ldx + k] : 0.f);
+      xs[mm * LDX + k] = P::cvt((row0 + mm < m && k < K) ? X.get((size_t)(row0 + mm) * ldx + k) : 0.f);
     }
     __syncthreads();
     for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
@@ -134,15 +163,15 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __rest
             const int n = n0 + c;
             if (n >= N) continue;
             float v = acc[i][j][c];
-            float* o = out + (size_t)row * ldo + n;
-            if (epi == EPI_ACC) v += *o;
+            const size_t o = (size_t)row * ldo + n;
+            if (epi == EPI_ACC) v += out.get(o);
             else if (epi == EPI_BIAS) v += W.b[n];
             else if (epi == EPI_BIAS_TANH) v = trk_tanh(v + W.b[n]);
             else if (epi == EPI_DTANH) {
-              const float a = aux[(size_t)row * ldaux + n];
+              const float a = aux.get((size_t)row * ldaux + n);
               v *= 1.f - a * a;
             }
-            *o = v;
+            out.set(o, v);
           }
         }
       }
@@ -159,7 +188,7 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(const float* __rest
 constexpr int WG_T = 64;   // tile edge (k and n)
 constexpr int WG_R = 64;   // rows staged per step
 
-__global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X, int ldx, const int* __restrict__ gsrc,
+__global__ __launch_bounds__(256) void wgrad_kernel(ActBuf X, int ldx, const int* __restrict__ gsrc,
                                                     const int* __restrict__ gdst, const float* __restrict__ S, int gd,
                                                     int gn, int K, int with_bias, const float* __restrict__ Dm, int ldd, int N,
                                                     int64_t m, int64_t rows_per_chunk, float* __restrict__ partial) {
@@ -181,7 +210,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X,
       if (row < rend) {
         if (k < K) {
           if (gsrc) xv = k < gd ? S[node_of(gsrc[row], gn) * gd + k] : S[node_of(gdst[row], gn) * gd + (k - gd)];
-          else xv = X[(size_t)row * ldx + k];
+          else xv = X.get((size_t)row * ldx + k);
         } else if (k == K && with_bias) {
           xv = 1.f;
         }
@@ -222,7 +251,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ X,
 // rows of one column are one 16-byte read; 32 rows per product.
 constexpr int WGB_LD = WG_R + 8;   // row stride of the transposed tiles (bf16 elements)
 
-__global__ __launch_bounds__(256) void wgrad_bf16_kernel(const float* __restrict__ X, int ldx,
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(ActBuf X, int ldx,
                                                          const int* __restrict__ gsrc, const int* __restrict__ gdst,
                                                          const float* __restrict__ S, int gd, int gn, int K,
                                                          int with_bias, const float* __restrict__ Dm, int ldd, int N,
@@ -245,7 +274,7 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const float* __restrict
       if (row < rend) {
         if (k < K) {
           if (gsrc) xv = k < gd ? S[node_of(gsrc[row], gn) * gd + k] : S[node_of(gdst[row], gn) * gd + (k - gd)];
-          else xv = X[(size_t)row * ldx + k];
+          else xv = X.get((size_t)row * ldx + k);
         } else if (k == K && with_bias) {
           xv = 1.f;
         }
@@ -290,7 +319,7 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunk
 }
 
 // per-node sums of rows of M [m][H] over incidence lists (src, dst or both), fixed order
-__global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __restrict__ p1, const int* __restrict__ i1,
+__global__ void segsum_kernel(ActBuf M, int H, const int* __restrict__ p1, const int* __restrict__ i1,
                               const int* __restrict__ p2, const int* __restrict__ i2, int n, float* __restrict__ out,
                               int ldo, float sign2) {
   const int waves = gridDim.x * (blockDim.x >> 6);
@@ -299,10 +328,10 @@ __global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __r
     for (int c = l; c < H; c += 64) {
       float s = 0.f;
       if (p1)
-        for (int k = p1[node]; k < p1[node + 1]; ++k) s += M[(size_t)i1[k] * H + c];
+        for (int k = p1[node]; k < p1[node + 1]; ++k) s += M.get((size_t)i1[k] * H + c);
       if (p2) {
         float s2 = 0.f;
-        for (int k = p2[node]; k < p2[node + 1]; ++k) s2 += M[(size_t)i2[k] * H + c];
+        for (int k = p2[node]; k < p2[node + 1]; ++k) s2 += M.get((size_t)i2[k] * H + c);
         s += sign2 * s2;
       }
       out[(size_t)node * ldo + c] = s;
@@ -314,32 +343,32 @@ __global__ void segsum_kernel(const float* __restrict__ M, int H, const int* __r
 // elementwise kernels
 // ---------------------------------------------------------------------------
 // X[r] = [S[src[r]] | S[dst[r]]], width 2*d (ld = ldx)
-__global__ void pair_gather_kernel(const float* S, int d, int n, const int* src, const int* dst, int64_t m, float* X,
+__global__ void pair_gather_kernel(const float* S, int d, int n, const int* src, const int* dst, int64_t m, ActBuf X,
                                    int ldx) {
   GRID_STRIDE(i, m * 2 * d) {
     const int64_t r = i / (2 * d);
     const int c = (int)(i - r * 2 * d);
-    X[r * ldx + c] = c < d ? S[node_of(src[r], n) * d + c] : S[node_of(dst[r], n) * d + c - d];
+    X.set(r * ldx + c, c < d ? S[node_of(src[r], n) * d + c] : S[node_of(dst[r], n) * d + c - d]);
   }
 }
 // t = tanh(A + P[src][0:H] + P[dst][H:2H] + b)
 __global__ void pre_tanh_kernel(const float* A, const float* P, const float* b, const int* src, const int* dst, int n,
-                                int64_t m, int H, float* t) {
+                                int64_t m, int H, ActBuf t) {
   GRID_STRIDE(i, m * H) {
     const int64_t r = i / H;
     const int c = (int)(i - r * H);
-    t[i] = trk_tanh(A[i] + P[node_of(src[r], n) * 2 * H + c] + P[node_of(dst[r], n) * 2 * H + H + c] + b[c]);
+    t.set(i, trk_tanh(A[i] + P[node_of(src[r], n) * 2 * H + c] + P[node_of(dst[r], n) * 2 * H + H + c] + b[c]));
   }
 }
-__global__ void add_kernel(const float* a, const float* b, float* out, int64_t count) {
-  GRID_STRIDE(i, count) out[i] = a[i] + b[i];
+__global__ void add_kernel(ActBuf a, const float* b, ActBuf out, int64_t count) {
+  GRID_STRIDE(i, count) out.set(i, a.get(i) + b[i]);
 }
 // out[r][0:H] = A[r], out[r][H:2H] = B[r]
-__global__ void concat_kernel(const float* A, const float* B, int64_t n, int H, float* out) {
+__global__ void concat_kernel(ActBuf A, const float* B, int64_t n, int H, float* out) {
   GRID_STRIDE(i, n * 2 * H) {
     const int64_t r = i / (2 * H);
     const int c = (int)(i - r * 2 * H);
-    out[i] = c < H ? A[r * H + c] : B[r * H + c - H];
+    out[i] = c < H ? A.get(r * H + c) : B[r * H + c - H];
   }
 }
 // de[e] += dm[src[e]] + dm[dst[e]]   (dm rows with stride ldm, H columns)
@@ -352,11 +381,11 @@ __global__ void gather_add_kernel(const float* dm, int ldm, const int* src, cons
   }
 }
 // out[r][c] = dz[r] * w[c] * (1 - u[r][c]^2)
-__global__ void outgrad_kernel(const float* dz, const float* w, const float* u, int64_t m, int H, float* out) {
+__global__ void outgrad_kernel(const float* dz, const float* w, ActBuf u, int64_t m, int H, float* out) {
   GRID_STRIDE(i, m * H) {
     const int64_t r = i / H;
     const int c = (int)(i - r * H);
-    const float a = u[i];
+    const float a = u.get(i);
     out[i] = dz[r] * w[c] * (1.f - a * a);
   }
 }
@@ -369,8 +398,11 @@ __global__ void add_cols_kernel(const float* a, const float* b, int ldb, int64_t
   }
 }
 // out = d * (1 - a^2)
-__global__ void dtanh_kernel(const float* d, const float* a, int64_t count, float* out) {
-  GRID_STRIDE(i, count) out[i] = d[i] * (1.f - a[i] * a[i]);
+__global__ void dtanh_kernel(const float* d, ActBuf a, int64_t count, float* out) {
+  GRID_STRIDE(i, count) {
+    const float v = a.get(i);
+    out[i] = d[i] * (1.f - v * v);
+  }
 }
 
 // bce: per-block partial loss sums (fixed order) and dz = (sigmoid(z) - y) / m
@@ -494,9 +526,10 @@ struct TrainState {
   DevLayer ne2T, ee2T, ecT, eabT, e2T, n1T, n2T, ocT, oabT;        // transposed
   // buffers
   Arena arena;
-  float *fx0 = nullptr, *fact = nullptr, *fdel0 = nullptr, *fdel1 = nullptr;
-  float *x6 = nullptr, *ea1 = nullptr, *na1 = nullptr, *hck = nullptr, *eck = nullptr;
-  float *P = nullptr, *pre = nullptr, *t1 = nullptr, *v = nullptr, *u = nullptr;
+  // activations kept from forward to backward (BF16 in a BF16 context)
+  ActBuf fx0, fact, x6, ea1, na1, hck, eck, u, eact;
+  float *fdel0 = nullptr, *fdel1 = nullptr;
+  float *P = nullptr, *pre = nullptr, *t1 = nullptr, *v = nullptr;
   float *de = nullptr, *dpre = nullptr, *dpre1 = nullptr, *msg = nullptr, *nin = nullptr, *q1 = nullptr, *q2 = nullptr;
   float *dh = nullptr, *dh2 = nullptr, *dq = nullptr, *dq1 = nullptr, *dnin = nullptr, *dP = nullptr, *tmpN = nullptr;
   float* partial = nullptr;
@@ -504,7 +537,7 @@ struct TrainState {
   float* bce_part = nullptr;
   int64_t cap_c = 0, cap_f = 0, nmax = 0;
   // embedding training
-  float *eact = nullptr, *edel0 = nullptr, *edel1 = nullptr, *pg = nullptr;
+  float *edel0 = nullptr, *edel1 = nullptr, *pg = nullptr;
   int* pcounts = nullptr;
   GnnScratch pairs;     // incidence lists of the pairs (by first and by second hit)
 };
@@ -612,8 +645,8 @@ MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
 }
 
 template <class P, int NTW>
-void rowgemm_t(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
-               const float* aux, int ldaux, int n_cu, hipStream_t s) {
+void rowgemm_t(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
+               ActBuf aux, int ldaux, int n_cu, hipStream_t s) {
   if (W.nkb * P::KB <= 512) {
     const int64_t tiles = (m + 63) / 64;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
@@ -628,8 +661,8 @@ void rowgemm_t(const float* X, int ldx, int K, int64_t m, const DevLayer& W, flo
 }
 
 template <class P>
-void rowgemm_p(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
-               const float* aux, int ldaux, int n_cu, hipStream_t s) {
+void rowgemm_p(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
+               ActBuf aux, int ldaux, int n_cu, hipStream_t s) {
   const int per_wave = (W.nnt + RG_NW - 1) / RG_NW;
   if (per_wave <= 1) rowgemm_t<P, 1>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
   else if (per_wave <= 2) rowgemm_t<P, 2>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
@@ -637,13 +670,13 @@ void rowgemm_p(const float* X, int ldx, int K, int64_t m, const DevLayer& W, flo
 }
 
 // out = epi(X W) with W's blocks in the training precision (bf16: BF16 blocks)
-void rowgemm(const float* X, int ldx, int K, int64_t m, const DevLayer& W, float* out, int ldo, int N, int epi,
-             const float* aux, int ldaux, int n_cu, hipStream_t s, bool bf16) {
+void rowgemm(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
+             ActBuf aux, int ldaux, int n_cu, hipStream_t s, bool bf16) {
   if (bf16) rowgemm_p<PrecBF16>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
   else rowgemm_p<PrecF32>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
 }
 
-void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int gn,
+void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int gn,
            int K, bool bias, const float* D, int ldd, int N, int64_t m, float* grad, hipStream_t s) {
   const int Kb = K + (bias ? 1 : 0);
   const int64_t count = (int64_t)Kb * N;
@@ -661,7 +694,7 @@ void wgrad(TrainState& T, const float* X, int ldx, const int* gsrc, const int* g
   }
 }
 
-void segsum(const float* M, int H, const int* p1, const int* i1, const int* p2, const int* i2, int n, float* out, int ldo,
+void segsum(ActBuf M, int H, const int* p1, const int* i1, const int* p2, const int* i2, int n, float* out, int ldo,
             hipStream_t s, float sign2 = 1.f) {
   segsum_kernel<<<blocks_for(n, 4, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo, sign2);
 }
@@ -711,24 +744,29 @@ int train_create(trk_ctx* c) {
   T->cap_f = CF;
   T->nmax = NH;
   Arena& a = T->arena;
-  a.add(T->fx0, (size_t)CC * 2 * D);
-  a.add(T->fact, (size_t)L * CC * F);
+  auto act = [&](ActBuf& b, size_t count) {
+    b.bf16 = T->bf16 ? 1 : 0;
+    a.add_bytes(b.p, count * (T->bf16 ? 2 : 4));
+  };
+  act(T->fx0, (size_t)CC * 2 * D);
+  act(T->fact, (size_t)L * CC * F);
   a.add(T->fdel0, (size_t)CC * F);
   a.add(T->fdel1, (size_t)CC * F);
-  a.add(T->x6, (size_t)CF * 6);
-  a.add(T->ea1, (size_t)CF * H);
-  a.add(T->na1, (size_t)NH * H);
-  a.add(T->hck, (size_t)(It + 1) * NH * H);
-  a.add(T->eck, (size_t)(It + 1) * CF * H);
+  act(T->x6, (size_t)CF * 6);
+  act(T->ea1, (size_t)CF * H);
+  act(T->na1, (size_t)NH * H);
+  act(T->hck, (size_t)(It + 1) * NH * H);
+  act(T->eck, (size_t)(It + 1) * CF * H);
+  act(T->u, (size_t)CF * H);
   a.add(T->P, (size_t)NH * 2 * H);
-  for (float** p : {&T->pre, &T->t1, &T->v, &T->u, &T->de, &T->dpre, &T->dpre1}) a.add(*p, (size_t)CF * H);
+  for (float** p : {&T->pre, &T->t1, &T->v, &T->de, &T->dpre, &T->dpre1}) a.add(*p, (size_t)CF * H);
   a.add(T->msg, (size_t)NH * H);
   a.add(T->nin, (size_t)NH * 2 * H);
   for (float** p : {&T->q1, &T->q2, &T->dh, &T->dh2, &T->dq, &T->dq1, &T->tmpN}) a.add(*p, (size_t)NH * H);
   a.add(T->dnin, (size_t)NH * 2 * H);
   a.add(T->dP, (size_t)NH * 2 * H);
   T->partial_floats = std::max<int64_t>((int64_t)16 * 513 * 512, (int64_t)8 * (EW + 1) * EW);
-  a.add(T->eact, (size_t)EL * NH * EW);
+  act(T->eact, (size_t)EL * NH * EW);
   a.add(T->edel0, (size_t)NH * EW);
   a.add(T->edel1, (size_t)NH * EW);
   a.add(T->pg, (size_t)CC * k.emb_dim);
@@ -861,10 +899,10 @@ int trk_filter_train_fwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
   TrainState& T = *c->train;
   const int D = c->cfg.emb_dim, F = c->cfg.filt_hidden, L = c->cfg.filt_layers;
   ew(pair_gather_kernel, m * 2 * D, s, d_emb, D, (int)n, d_src, d_dst, m, T.fx0, 2 * D);
-  const float* a = T.fx0;
+  ActBuf a = T.fx0;
   int lda = 2 * D, K = 2 * D;
   for (int i = 0; i < L; ++i) {
-    float* o = T.fact + (size_t)i * T.cap_c * F;
+    ActBuf o = T.fact.at((size_t)i * T.cap_c * F);
     rowgemm(a, lda, K, m, T.filtF[i], o, F, F, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     a = o;
     lda = F;
@@ -882,7 +920,7 @@ int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
   if (m == 0) return TRK_OK;
   TrainState& T = *c->train;
   const int D = c->cfg.emb_dim, F = c->cfg.filt_hidden, L = c->cfg.filt_layers;
-  const float* aL = T.fact + (size_t)(L - 1) * T.cap_c * F;
+  const ActBuf aL = T.fact.at((size_t)(L - 1) * T.cap_c * F);
   wgrad(T, aL, F, nullptr, nullptr, nullptr, 0, 0, F, true, d_dlogits, 1, 1, m, d_grads + T.filt[L].w, s);
   float* del = T.fdel0;
   float* nxt = T.fdel1;
@@ -891,10 +929,11 @@ int trk_filter_train_bwd(trk_ctx* c, const float* d_emb, int64_t n, const int32_
     if (i == 0)
       wgrad(T, nullptr, 0, d_src, d_dst, d_emb, D, (int)n, 2 * D, true, del, F, F, m, d_grads + T.filt[0].w, s);
     else
-      wgrad(T, T.fact + (size_t)(i - 1) * T.cap_c * F, F, nullptr, nullptr, nullptr, 0, 0, F, true, del, F, F, m,
+      wgrad(T, T.fact.at((size_t)(i - 1) * T.cap_c * F), F, nullptr, nullptr, nullptr, 0, 0, F, true, del, F, F, m,
             d_grads + T.filt[i].w, s);
     if (i >= 1) {
-      rowgemm(del, F, F, m, T.filtT[i], nxt, F, F, EPI_DTANH, T.fact + (size_t)(i - 1) * T.cap_c * F, F, c->n_cu, s, T.bf16);
+      rowgemm(del, F, F, m, T.filtT[i], nxt, F, F, EPI_DTANH, T.fact.at((size_t)(i - 1) * T.cap_c * F), F, c->n_cu, s,
+              T.bf16);
       std::swap(del, nxt);
     }
   }
@@ -917,10 +956,10 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   rowgemm(T.x6, 6, 6, m, T.ee1, T.ea1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
   rowgemm(T.ea1, H, H, m, T.ee2, T.eck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
   for (int t = 1; t <= It; ++t) {
-    const float* h = T.hck + (size_t)(t - 1) * T.nmax * H;
-    const float* e = T.eck + (size_t)(t - 1) * T.cap_f * H;
-    float* h_new = T.hck + (size_t)t * T.nmax * H;
-    float* e_new = T.eck + (size_t)t * T.cap_f * H;
+    const ActBuf h = T.hck.at((size_t)(t - 1) * T.nmax * H);
+    const ActBuf e = T.eck.at((size_t)(t - 1) * T.cap_f * H);
+    const ActBuf h_new = T.hck.at((size_t)t * T.nmax * H);
+    const ActBuf e_new = T.eck.at((size_t)t * T.cap_f * H);
     rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
@@ -932,8 +971,8 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
     rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     ew(add_kernel, n * H, s, h, T.q2, h_new, n * H);
   }
-  const float* hT = T.hck + (size_t)It * T.nmax * H;
-  const float* eT = T.eck + (size_t)It * T.cap_f * H;
+  const ActBuf hT = T.hck.at((size_t)It * T.nmax * H);
+  const ActBuf eT = T.eck.at((size_t)It * T.cap_f * H);
   rowgemm(hT, H, H, n, T.oab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
   if (m > 0) {
     rowgemm(eT, H, H, m, T.oc, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
@@ -954,8 +993,8 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   const int H = c->cfg.gnn_hidden, It = c->cfg.gnn_iters;
   const int nn = (int)n;
   float* G = d_grads;
-  const float* hT = T.hck + (size_t)It * T.nmax * H;
-  const float* eT = T.eck + (size_t)It * T.cap_f * H;
+  const ActBuf hT = T.hck.at((size_t)It * T.nmax * H);
+  const ActBuf eT = T.eck.at((size_t)It * T.cap_f * H);
   // output head
   wgrad(T, T.u, H, nullptr, nullptr, nullptr, 0, 0, H, true, d_dlogits, 1, 1, m, G + T.out[1].w, s);
   float* du = T.dpre1;
@@ -970,9 +1009,9 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   rowgemm(T.dP, 2 * H, 2 * H, n, T.oabT, dh, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
   rowgemm(du, H, H, m, T.ocT, T.de, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
   for (int t = It; t >= 1; --t) {
-    const float* h = T.hck + (size_t)(t - 1) * T.nmax * H;
-    const float* e = T.eck + (size_t)(t - 1) * T.cap_f * H;
-    const float* e_new = T.eck + (size_t)t * T.cap_f * H;
+    const ActBuf h = T.hck.at((size_t)(t - 1) * T.nmax * H);
+    const ActBuf e = T.eck.at((size_t)(t - 1) * T.cap_f * H);
+    const ActBuf e_new = T.eck.at((size_t)t * T.cap_f * H);
     // recompute this iteration's internals from (h^{t-1}, e^{t-1})
     rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
     rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
@@ -1024,10 +1063,10 @@ int trk_embed_train_fwd(trk_ctx* c, const float* d_x, int64_t n, float* d_emb, h
   if (n == 0) return TRK_OK;
   TrainState& T = *c->train;
   const int EL = c->cfg.emb_layers, EW = c->cfg.emb_hidden, D = c->cfg.emb_dim;
-  const float* a = d_x;
+  ActBuf a = d_x;
   int lda = 3, K = 3;
   for (int i = 0; i < EL; ++i) {
-    float* o = T.eact + (size_t)i * T.nmax * EW;
+    ActBuf o = T.eact.at((size_t)i * T.nmax * EW);
     rowgemm(a, lda, K, n, T.embF[i], o, EW, EW, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     a = o;
     lda = EW;
@@ -1043,7 +1082,7 @@ int trk_embed_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const float* d_
   if (n == 0) return TRK_OK;
   TrainState& T = *c->train;
   const int EL = c->cfg.emb_layers, EW = c->cfg.emb_hidden, D = c->cfg.emb_dim;
-  auto act = [&](int i) { return T.eact + (size_t)(i - 1) * T.nmax * EW; };   // a_i, i = 1..EL
+  auto act = [&](int i) { return T.eact.at((size_t)(i - 1) * T.nmax * EW); };   // a_i, i = 1..EL
   // output layer: emb = a_EL W + b (linear)
   wgrad(T, act(EL), EW, nullptr, nullptr, nullptr, 0, 0, EW, true, d_demb, D, D, n, d_grads + T.emb[EL].w, s);
   float* del = T.edel0;

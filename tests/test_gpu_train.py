@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from oracle import train as OT
-from gen import TINY, make_weights, generate_event
+from gen import TINY, MU200, make_weights, generate_event
 
 pytestmark = pytest.mark.gpu
 
@@ -339,3 +339,24 @@ def test_bf16_embedding_training_gradient():
     # the pair gradient is taken at the BF16 forward's own embedding, whose error adds
     # to that of the backward products: twice the per-network bound
     assert ee <= 0.05 and max(errs) <= 2 * GRAD_RTOL_BF16
+
+
+def test_bf16_context_keeps_its_activations_in_bf16():
+    """A BF16 training context stores what the forward keeps for the backward (the
+    filter's hidden layers, the per-iteration states, the encoders' and the output
+    head's hidden layers, the embedding's hidden layers) in BF16: with the full-size
+    network and the same capacities it holds markedly less device memory than an
+    FP32 context (the FP32 deltas and scratch are the same in both)."""
+    from paper_2501_05520_amd.training import TrainContext
+    cfg = MU200
+    nets = make_weights(cfg, 0)
+    held = {}
+    for prec in ("fp32", "bf16"):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        tc = TrainContext(cfg, nets, max_hits=50_000, max_cand_edges=500_000, max_kept_edges=500_000, precision=prec)
+        torch.cuda.synchronize()
+        held[prec] = free0 - torch.cuda.mem_get_info()[0]
+        tc.close()
+    print(f"training context memory: fp32 {held['fp32'] / 2**30:.2f} GiB, bf16 {held['bf16'] / 2**30:.2f} GiB")
+    assert held["bf16"] < 0.8 * held["fp32"]
