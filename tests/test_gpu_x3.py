@@ -13,7 +13,8 @@ import torch
 
 import oracle
 from gen import TINY, MU200, make_weights, generate_event
-from tests.gpu_helpers import compare_edges, label_agreement
+from tests.chain_parity import chain_parity
+from tests.gpu_helpers import label_agreement
 
 pytestmark = pytest.mark.gpu
 
@@ -48,11 +49,6 @@ def tiny_ref(tiny_nets):
     return out
 
 
-def _margin(r, cfg, tol):
-    return int(np.sum(np.abs(r["filter_scores"] - cfg.filter_cut) <= tol)) + \
-        int(np.sum(np.abs(r["gnn_scores"] - cfg.score_cut) <= tol))
-
-
 @pytest.mark.parametrize("seed", SEEDS)
 def test_tiny_stages(tiny_pipe, tiny_ref, tiny_nets, seed):
     ev, r = tiny_ref[seed]
@@ -67,23 +63,14 @@ def test_tiny_stages(tiny_pipe, tiny_ref, tiny_nets, seed):
 
 
 @pytest.mark.parametrize("seed", SEEDS)
-def test_tiny_end_to_end(tiny_pipe, tiny_ref, seed):
+def test_tiny_end_to_end(tiny_pipe, tiny_ref, tiny_nets, seed):
+    """The split-BF16 chain end to end, held to the FP32 bars: trk_event equals the
+    staged calls, and the oracle's chain with the GPU's decision taken only on
+    margin edges (and on candidate pairs within the embedding error of the radius or
+    K-th distance) gives identical labels; no fallback."""
     ev, r = tiny_ref[seed]
-    labels, info = tiny_pipe.event(ev.x)
-    labels = labels.cpu().numpy()
-    e32 = r["emb"].astype(np.float32)
-    rad = float(np.float32(TINY.radius))
-    lo, hi, d2 = oracle.radius_pairs(e32, rad)
-    # the chain's graph is built on its own embedding: edges may differ from the
-    # oracle's only for pairs within the embedding error of the radius or K-th distance
-    src, dst, _ = tiny_pipe.build_graph(tiny_pipe.embed(ev.x))
-    os_, od, _ = oracle.radius_graph(e32, rad, TINY.k_max)
-    ndiff, _, _ = compare_edges(e32, src.cpu().numpy(), dst.cpu().numpy(), os_, od, rad, TINY.k_max, lo, hi, d2)
-    if _margin(r, TINY, SCORE_TOL) == 0 and ndiff == 0:
-        assert np.array_equal(labels, r["labels"])
-    else:
-        hit, jac = label_agreement(labels, r["labels"])
-        assert hit >= 0.99
+    st = chain_parity(tiny_pipe, ev.x, tiny_nets, EMB_TOL, SCORE_TOL)
+    print(f"bf16x3 tiny seed {seed}: {st}")
 
 
 @pytest.fixture(scope="module")
