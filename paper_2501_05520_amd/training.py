@@ -148,13 +148,14 @@ def positive_pairs(pid, layer, reach=2):
     return np.concatenate(pa), np.concatenate(pb)
 
 
-def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0, neg_weight=10.0):
+def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0, neg_weight=10.0, measure=False):
     """One metric-learning step on event ev: positives from the truth, hard
     negatives from the current radius graph, uniform random negatives, the
     negative term weighted by neg_weight (without it the positive term dominates
     and the embedding contracts: every point ends up within r of ~100 others);
     returns (loss, true-edge fraction of the current candidate graph, its edge
-    count)."""
+    count) and, with measure, the fraction of the positive pairs that the current
+    candidate graph holds."""
     dev = tc.device
     x = torch.as_tensor(ev.x, device=dev)
     emb = torch.empty((ev.n, tc.cfg.emb_dim), device=dev)
@@ -162,10 +163,11 @@ def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0, neg_weig
     cap = int(tc.config.max_cand_edges)
     cs = torch.empty(cap, dtype=torch.int32, device=dev)
     cd = torch.empty_like(cs)
-    try:
-        ne, _ = trk.trk_build_graph(tc.ctx, emb, cs, cd)
-    except trk.TrkError:
-        ne = 0
+    # a graph above the capacity still yields its first `cap` edges (the rows of the
+    # lowest ids, a random subset of hits since ids are shuffled): hard negatives
+    # keep coming when the embedding contracts, which is when they are needed most
+    total, _ = trk.trk_build_graph(tc.ctx, emb, cs, cd, truncate_ok=True)
+    ne = min(total, cap)
     cs_h, cd_h = cs[:ne].cpu().numpy(), cd[:ne].cpu().numpy()
     yc = edge_truth(ev.pid, cs_h, cd_h) if ne else np.zeros(0, np.float32)
     true_frac = float(yc.mean()) if ne else 0.0
@@ -191,7 +193,13 @@ def embedding_step(tc, ev, rng, margin, lr, n_random=2.0, max_hard=2.0, neg_weig
     grads = torch.zeros(tc.n_params, device=dev)
     trk.trk_embed_train_bwd(tc.ctx, x, demb, grads)
     tc.adam_step(grads, lr)
-    return loss, true_frac, int(ne)
+    if not measure:
+        return loss, true_frac, int(total)
+    n = np.int64(ev.n)
+    pos = np.minimum(pa, pb).astype(np.int64) * n + np.maximum(pa, pb)
+    cand = cs_h.astype(np.int64) * n + cd_h
+    eff = float(np.isin(pos, cand).mean()) if pos.size and total <= cap else float("nan")
+    return loss, true_frac, int(total), eff
 
 
 def pipeline_step(tc, ev, lr, filter=True, gnn=True):
@@ -236,3 +244,63 @@ def filter_scores_on(tc, ev):
     kd = torch.empty_like(ks)
     trk.trk_filter(tc.ctx, emb, cs, cd, scores, ks[:kcap], kd[:kcap])
     return scores.cpu().numpy(), edge_truth(ev.pid, cs.cpu().numpy(), cd.cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# data-dependent start of the first layers that read an edge's two ends
+# ---------------------------------------------------------------------------
+def fold_pair_standardisation(w, b, a_s, a_t):
+    """First-layer weights acting on u = [a_s, a_t] that compute the seeded layer
+    (w, b) of the standardised pair mean m = (a_s + a_t) / 2 and difference
+    d = a_s - a_t (statistics over the rows of a_s, a_t): with A, B the two halves of
+    w, W_s = A / (2 sd_m) + B / sd_d, W_t = A / (2 sd_m) - B / sd_d and
+    b' = b - (A mu_m / sd_m + B mu_d / sd_d).  The small difference between the two
+    ends of an edge, which carries the track signal, is then seen at unit scale."""
+    a_s = np.asarray(a_s, np.float64)
+    a_t = np.asarray(a_t, np.float64)
+    m, d = (a_s + a_t) / 2, a_s - a_t
+    mu_m, sd_m = m.mean(0), m.std(0) + 1e-9
+    mu_d, sd_d = d.mean(0), d.std(0) + 1e-9
+    w = np.asarray(w, np.float64)
+    D = w.shape[0] // 2
+    A, B = w[:D], w[D:]
+    ws = A / (2 * sd_m[:, None]) + B / sd_d[:, None]
+    wt = A / (2 * sd_m[:, None]) - B / sd_d[:, None]
+    b2 = np.asarray(b, np.float64) - (mu_m / sd_m) @ A - (mu_d / sd_d) @ B
+    return np.concatenate([ws, wt]).astype(np.float32), b2.astype(np.float32)
+
+
+def pair_samples(pipe, events):
+    """Embedding pairs, feature pairs (over the candidate edges) and the features
+    of the given events, from an inference Pipeline (host arrays)."""
+    emb_pairs, x_pairs, xs = [], [], []
+    for ev in events:
+        e = pipe.embed(ev.x)
+        s, d, _ = pipe.build_graph(e)
+        s, d = s.cpu().numpy(), d.cpu().numpy()
+        en = e.cpu().numpy()
+        emb_pairs.append((en[s], en[d]))
+        x_pairs.append((ev.x[s], ev.x[d]))
+        xs.append(ev.x)
+    cat = lambda ps, i: np.concatenate([p[i] for p in ps])
+    return (cat(emb_pairs, 0), cat(emb_pairs, 1)), (cat(x_pairs, 0), cat(x_pairs, 1)), np.concatenate(xs)
+
+
+def standardised_start(nets, emb_pairs, x_pairs, x, filter=True, gnn=True):
+    """nets with the filter's first layer (filter) and the edge and node encoders'
+    first layers (gnn) reading standardised inputs: pair mean and difference for the
+    layers that read both ends of an edge, the features themselves for the node
+    encoder."""
+    out = dict(nets)
+    if filter:
+        w, b = fold_pair_standardisation(*nets["filt"][0], *emb_pairs)
+        out["filt"] = [(w, b)] + list(nets["filt"][1:])
+    if gnn:
+        w, b = fold_pair_standardisation(*nets["edge_enc"][0], *x_pairs)
+        out["edge_enc"] = [(w, b)] + list(nets["edge_enc"][1:])
+        xa = np.asarray(x, np.float64)
+        mu, sd = xa.mean(0), xa.std(0) + 1e-9
+        w0, b0 = [np.asarray(v, np.float64) for v in nets["node_enc"][0]]
+        out["node_enc"] = [((w0 / sd[:, None]).astype(np.float32), (b0 - (mu / sd) @ w0).astype(np.float32))] + \
+            list(nets["node_enc"][1:])
+    return out

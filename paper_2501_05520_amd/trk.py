@@ -212,10 +212,15 @@ def trk_embed(ctx, x, emb, stream=None):
     _check(lib().trk_embed(ctx, _ptr(x), x.shape[0], _ptr(emb), _stream(stream)), "trk_embed")
 
 
-def trk_build_graph(ctx, emb, src, dst, stream=None):
+def trk_build_graph(ctx, emb, src, dst, stream=None, truncate_ok=False):
+    """Returns (total edge count, saturated count).  With truncate_ok a total above
+    the capacity is returned instead of raised: the first src.numel() edges of the
+    sorted list are then written."""
     ne, ns = ctypes.c_int64(), ctypes.c_int64()
     rc = lib().trk_build_graph(ctx, _ptr(emb), emb.shape[0], _ptr(src), _ptr(dst), src.numel(),
                                ctypes.byref(ne), ctypes.byref(ns), _stream(stream))
+    if rc == -3 and truncate_ok:
+        return ne.value, ns.value
     if rc == -3:
         raise TrkError(rc, f"trk_build_graph (needs {ne.value} edges)")
     _check(rc, "trk_build_graph")
