@@ -10,9 +10,10 @@ the stated tolerance of a threshold:
     within the band of r or of a saturated point's K-th distance; the band is the
     FP32 distance band widened by the bound 2 sqrt(D) max|emb_gpu - emb_oracle|
     on how far the GPU's embedding moves a distance;
-  * filter cut: every score within `score_tol` of the oracle's, and the GPU's
-    keep decision equal to the oracle's on every edge whose oracle score is more
-    than `score_tol` from the cut;
+  * filter cut: every score within `score_tol` of the oracle's filter on the GPU's
+    own embedding (itself checked against the oracle's), and the GPU's keep decision
+    equal to the oracle's on every edge whose oracle score is more than `score_tol`
+    from the cut;
   * interaction network and score cut: the same, on the GPU's filtered edges.
 
 With those decisions the oracle's components must equal the GPU's labels bit for
@@ -70,10 +71,16 @@ def chain_parity(pipe, x, nets, emb_tol, score_tol=1e-4, min_hits=3):
     assert nbad == 0, ("candidate edges outside the bands", det)
     assert abs(g["nsat"] - int((cnt > cfg.k_max).sum())) <= ndiff
 
-    # filter on the GPU's candidate edges
-    pf_o = oracle.filter_scores(emb_o, g["src"], g["dst"], nets)
+    # filter on the GPU's candidate edges, fed the GPU's own embedding (checked above
+    # against the oracle's): a filter that reads the small difference between an
+    # edge's two ends multiplies the embedding's own FP32 error, so each stage is
+    # compared on the same inputs, as in the stage tests; the figure on the oracle's
+    # FP64 embedding is reported beside it
+    pf_o = oracle.filter_scores(g["emb"], g["src"], g["dst"], nets)
     dpf = np.abs(g["pf"] - pf_o)
     assert dpf.size == 0 or dpf.max() <= score_tol, ("filter scores", dpf.max())
+    pf_o64 = oracle.filter_scores(emb_o, g["src"], g["dst"], nets)
+    dpf64 = np.abs(g["pf"] - pf_o64)
     cf = np.float32(cfg.filter_cut)
     keep_o = pf_o > cf
     keep_g = g["pf"] > cf
@@ -103,5 +110,6 @@ def chain_parity(pipe, x, nets, emb_tol, score_tol=1e-4, min_hits=3):
                 margin_filter=int(margin_f.sum()), margin_score=int(margin_s.sum()),
                 flips_filter=int(np.sum(keep_g != keep_o)), flips_score=int(np.sum(kept_g != kept_o)),
                 emb_rel_max=float(rel.max()), filter_dp_max=float(dpf.max()) if dpf.size else 0.0,
+                filter_dp_max_on_fp64_embedding=float(dpf64.max()) if dpf64.size else 0.0,
                 gnn_dp_max=float(dq.max()) if dq.size else 0.0,
                 candidates=len(oracle.candidates(lab_ev, min_hits)))
