@@ -183,7 +183,10 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
 
 // ---------------------------------------------------------------------------
 // edge encoder: e0 = tanh(tanh([x_s, x_t] W1 + b1) W2 + b2)
-// (products in P, states stored in Q's format with scale se)
+// (products in P, states stored in Q's format with scale se).  With BF16 products
+// the first layer reads the ends' FP32 mean and difference, [(x_s + x_t) / 2,
+// x_s - x_t], rounded to BF16 (its weights stored for that form, the same function),
+// so that the small difference between the two ends keeps its own precision.
 // ---------------------------------------------------------------------------
 template <class P, class Q, int H, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __restrict__ x, int n,
@@ -197,26 +200,43 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
   const int64_t ntiles = (m + MT - 1) / MT;
+  constexpr bool MD = std::is_same<P, PrecBF16>::value;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
     {
       constexpr int IT = (MT * P::KB + NW * 64 - 1) / (NW * 64);
-      int node[IT];
+      int node[IT], node2[IT];
       float v[IT];
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
         const int mm = idx / P::KB, k = idx - mm * P::KB;
-        node[it] = -1;
-        if (idx < MT * P::KB && k < 6 && row0 + mm < m) node[it] = k < 3 ? src[row0 + mm] : dst[row0 + mm];
+        node[it] = node2[it] = -1;
+        if (idx < MT * P::KB && k < 6 && row0 + mm < m) {
+          if (MD) {
+            node[it] = src[row0 + mm];
+            node2[it] = dst[row0 + mm];
+          } else {
+            node[it] = k < 3 ? src[row0 + mm] : dst[row0 + mm];
+          }
+        }
       }
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
         const int k = idx % P::KB;
         v[it] = 0.f;
-        if ((unsigned)node[it] < (unsigned)n) v[it] = x[(size_t)node[it] * 3 + (k % 3)];
-        else if (node[it] != -1 && d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+        if (MD) {
+          if ((unsigned)node[it] < (unsigned)n && (unsigned)node2[it] < (unsigned)n) {
+            const float a = x[(size_t)node[it] * 3 + (k % 3)], b = x[(size_t)node2[it] * 3 + (k % 3)];
+            v[it] = k < 3 ? 0.5f * (a + b) : a - b;
+          } else if (node[it] != -1 && d_err) {
+            atomicOr(d_err, TRK_ERRBIT_INDEX);
+          }
+        } else {
+          if ((unsigned)node[it] < (unsigned)n) v[it] = x[(size_t)node[it] * 3 + (k % 3)];
+          else if (node[it] != -1 && d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+        }
       }
 #pragma unroll
       for (int it = 0; it < IT; ++it) {

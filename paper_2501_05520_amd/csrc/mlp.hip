@@ -96,6 +96,12 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
 // GPF: the next tile's gathered inputs are requested during the last layer's epilogue
 // (edge ends first, under the epilogue's arithmetic; then the embedding values), so
 // that the tile start does not wait for two dependent round trips to memory.
+// A BF16 first layer (P0 = PrecBF16) reads the pair's FP32 mean and difference,
+// [(e_s + e_t) / 2, e_s - e_t], rounded to BF16, with its weights stored for that form
+// ([W_s + W_t; (W_s - W_t) / 2], the same function): the two ends of a candidate edge
+// lie close together, and rounding each to BF16 before their difference is taken
+// would lose that difference, which carries the edge's signal, to the rounding of
+// the much larger coordinates.
 template <class P, class P0, int W, int MT, int NW, bool GPF = false>
 __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict__ emb, int D,
                                                          const int* __restrict__ src, const int* __restrict__ dst,
@@ -117,46 +123,102 @@ __global__ __launch_bounds__(NW * 64) void filter_kernel(const float* __restrict
   const int nlayers = 1 + hid.n;
   const int kin = 2 * D;
   const int kin_pad = l_in.nkb * P0::KB;
+  constexpr bool MD = std::is_same<P0, PrecBF16>::value;
   // the gathered inputs held in registers between tiles (GPF): this thread's entries
-  // idx = threadIdx.x + i * blockDim.x of the MT x kin_pad input tile
-  constexpr int GI = (MT * KIN_MAX + NW * 64 - 1) / (NW * 64);
-  int gnd[GI];
+  // idx = threadIdx.x + i * blockDim.x of the MT x kin_pad input tile (MD: of the
+  // MT x D pairs of the two ends' values)
+  constexpr int GI = (MT * (MD ? KIN_MAX / 2 : KIN_MAX) + NW * 64 - 1) / (NW * 64);
+  int gnd[GI], gnd2[GI];
   bool gok[GI];
-  float gv[GI];
+  float gv[GI], gv2[GI];
   auto gather_ends = [&](int64_t r0) {
 #pragma unroll
     for (int i = 0; i < GI; ++i) {
       const int idx = threadIdx.x + i * NW * 64;
-      const int mm = idx / kin_pad, k = idx - mm * kin_pad;
-      const int64_t e = r0 + mm;
-      gok[i] = idx < MT * kin_pad && e < m && k < kin;
-      gnd[i] = gok[i] ? ((k < D) ? src[e] : dst[e]) : 0;
+      if constexpr (MD) {
+        const int mm = idx / D;
+        const int64_t e = r0 + mm;
+        gok[i] = idx < MT * D && e < m;
+        gnd[i] = gok[i] ? src[e] : 0;
+        gnd2[i] = gok[i] ? dst[e] : 0;
+      } else {
+        const int mm = idx / kin_pad, k = idx - mm * kin_pad;
+        const int64_t e = r0 + mm;
+        gok[i] = idx < MT * kin_pad && e < m && k < kin;
+        gnd[i] = gok[i] ? ((k < D) ? src[e] : dst[e]) : 0;
+      }
     }
   };
   auto gather_values = [&]() {
 #pragma unroll
     for (int i = 0; i < GI; ++i) {
       const int idx = threadIdx.x + i * NW * 64;
-      const int k = idx % kin_pad;
-      gv[i] = 0.f;
-      if (gok[i]) {
-        if ((unsigned)gnd[i] < (unsigned)n_nodes) gv[i] = emb[(size_t)gnd[i] * D + (k < D ? k : k - D)];
-        else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+      gv[i] = gv2[i] = 0.f;
+      if constexpr (MD) {
+        const int k = idx % D;
+        if (gok[i]) {
+          if ((unsigned)gnd[i] < (unsigned)n_nodes && (unsigned)gnd2[i] < (unsigned)n_nodes) {
+            gv[i] = emb[(size_t)gnd[i] * D + k];
+            gv2[i] = emb[(size_t)gnd2[i] * D + k];
+          } else if (d_err) {
+            atomicOr(d_err, TRK_ERRBIT_INDEX);
+          }
+        }
+      } else {
+        const int k = idx % kin_pad;
+        if (gok[i]) {
+          if ((unsigned)gnd[i] < (unsigned)n_nodes) gv[i] = emb[(size_t)gnd[i] * D + (k < D ? k : k - D)];
+          else if (d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
+        }
       }
     }
   };
+  if constexpr (MD) {
+    // the padding columns [2D, kin_pad) of the input tile stay zero
+    for (int idx = threadIdx.x; idx < MT * (kin_pad - kin); idx += blockDim.x) {
+      const int mm = idx / (kin_pad - kin), c = idx - mm * (kin_pad - kin);
+      xin[mm * S::LDI + kin + c] = P0::cvt(0.f);
+    }
+  }
   if (GPF && (int64_t)blockIdx.x < ntiles) {
     gather_ends((int64_t)blockIdx.x * MT);
     gather_values();
   }
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
-    if constexpr (GPF) {
+    if constexpr (GPF && MD) {
+#pragma unroll
+      for (int i = 0; i < GI; ++i) {
+        const int idx = threadIdx.x + i * NW * 64;
+        const int mm = idx / D, k = idx - mm * D;
+        if (idx < MT * D) {
+          xin[mm * S::LDI + k] = P0::cvt(0.5f * (gv[i] + gv2[i]));
+          xin[mm * S::LDI + D + k] = P0::cvt(gv[i] - gv2[i]);
+        }
+      }
+    } else if constexpr (GPF) {
 #pragma unroll
       for (int i = 0; i < GI; ++i) {
         const int idx = threadIdx.x + i * NW * 64;
         const int mm = idx / kin_pad, k = idx - mm * kin_pad;
         if (idx < MT * kin_pad) xin[mm * S::LDI + k] = P0::cvt(gv[i]);
+      }
+    } else if constexpr (MD) {
+      for (int idx = threadIdx.x; idx < MT * D; idx += blockDim.x) {
+        const int mm = idx / D, k = idx - mm * D;
+        const int64_t e = row0 + mm;
+        float a = 0.f, b = 0.f;
+        if (e < m) {
+          const int sn = src[e], tn = dst[e];
+          if ((unsigned)sn < (unsigned)n_nodes && (unsigned)tn < (unsigned)n_nodes) {
+            a = emb[(size_t)sn * D + k];
+            b = emb[(size_t)tn * D + k];
+          } else if (d_err) {
+            atomicOr(d_err, TRK_ERRBIT_INDEX);
+          }
+        }
+        xin[mm * S::LDI + k] = P0::cvt(0.5f * (a + b));
+        xin[mm * S::LDI + D + k] = P0::cvt(a - b);
       }
     } else {
       for (int idx = threadIdx.x; idx < MT * kin_pad; idx += blockDim.x) {

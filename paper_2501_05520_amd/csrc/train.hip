@@ -86,7 +86,9 @@ struct MatView {
 };
 
 // M[k][n] for k < K, n < N, built from A and B: mode 0 = A only, 1 = [A | B] side by side
-// (B from column N1), 2 = [A ; B] stacked (B from row K1).
+// (B from column N1), 2 = [A ; B] stacked (B from row K1), 3 = A for the input
+// [(u_s + u_t) / 2, u_s - u_t] of two halves of width `split` (rows [A_s + A_t;
+// (A_s - A_t) / 2], the form the BF16 inference layers that read an edge's two ends use).
 __global__ void frag_fill_kernel(uint4* out, int nkb, int nnt, int K, int N, MatView A, MatView B, int mode, int split,
                                  int bf16) {
   const int64_t nblk = (int64_t)nkb * nnt * 64;
@@ -99,6 +101,7 @@ __global__ void frag_fill_kernel(uint4* out, int nkb, int nnt, int K, int N, Mat
       if (k >= K || n >= N) return 0.f;
       if (mode == 1 && n >= split) return B.at(k, n - split);
       if (mode == 2 && k >= split) return B.at(k - split, n);
+      if (mode == 3) return k < split ? A.at(k, n) + A.at(k + split, n) : 0.5f * (A.at(k - split, n) - A.at(k, n));
       return A.at(k, n);
     };
     uint4 o;
@@ -845,12 +848,18 @@ int train_set_params(trk_ctx* c, const float* P, hipStream_t s) {
   same(c->emb_in, T.emb[0], 0, 3);
   for (int i = 1; i < c->cfg.emb_layers; ++i) same(c->emb_hid.l[i - 1], T.emb[i], 0, T.emb[i].K);
   same(c->emb_out, T.emb[c->cfg.emb_layers], 0, T.emb[c->cfg.emb_layers].K);
-  same(c->filt_in, T.filt[0], 0, T.filt[0].K);
+  if (inf_bf16)   // the BF16 first layer reads the pair's mean and difference
+    fill(c->filt_in, T.filt[0].K, T.filt[0].N, view(P, T.filt[0]), none, 3, T.filt[0].K / 2, P + T.filt[0].b, 1, s);
+  else
+    same(c->filt_in, T.filt[0], 0, T.filt[0].K);
   for (int i = 1; i < L; ++i) same(c->filt_hid.l[i - 1], T.filt[i], 0, T.filt[i].K);
   DevGNN& G = c->gnn;
   same(G.node_enc1, T.ne[0], 0, 3);
   same(G.node_enc2, T.ne[1], 0, H);
-  same(G.edge_enc1, T.ee[0], 0, 6);
+  if (inf_bf16)
+    fill(G.edge_enc1, 6, T.ee[0].N, view(P, T.ee[0]), none, 3, 3, P + T.ee[0].b, 1, s);
+  else
+    same(G.edge_enc1, T.ee[0], 0, 6);
   same(G.edge_enc2, T.ee[1], 0, H);
   same(G.edge_c, T.en[0], 2 * H, H);
   same(G.edge_ab, T.en[0], 0, H, view(P, T.en[0], H), 1);

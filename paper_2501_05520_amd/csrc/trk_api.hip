@@ -149,6 +149,20 @@ HostLinear rows_of(const HostLinear& L, int r0, int K, bool bias) {
   return o;
 }
 
+// The same layer for the input [(u_s + u_t) / 2, u_s - u_t] instead of [u_s, u_t]
+// (u_s, u_t of width D): rows [W_s + W_t; (W_s - W_t) / 2].  Used where a BF16 layer
+// reads the two ends of an edge, so that their difference is formed before rounding.
+HostLinear mean_diff_form(const HostLinear& L, int D) {
+  HostLinear o = L;
+  for (int k = 0; k < D; ++k)
+    for (int n = 0; n < L.N; ++n) {
+      const double ws = L.w[(size_t)k * L.N + n], wt = L.w[(size_t)(D + k) * L.N + n];
+      o.w[(size_t)k * L.N + n] = (float)(ws + wt);
+      o.w[(size_t)(D + k) * L.N + n] = (float)(0.5 * (ws - wt));
+    }
+  return o;
+}
+
 // [rows a-block | rows b-block] side by side: K x 2N
 HostLinear side_by_side(const HostLinear& L, int ra, int rb, int K) {
   HostLinear o;
@@ -273,7 +287,8 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   c->emb_hid.n = k.emb_layers - 1;
   for (int i = 1; i < k.emb_layers; ++i) up.layer(c->emb_hid.l[i - 1], emb[i], prec_emb);
   up.layer(c->emb_out, emb[k.emb_layers], prec_emb);
-  up.layer(c->filt_in, filt[0], prec_in);
+  // a BF16 first layer reads the pair's mean and difference (filter_kernel)
+  up.layer(c->filt_in, prec_in == TRK_PREC_BF16 ? mean_diff_form(filt[0], D) : filt[0], prec_in);
   c->filt_hid.n = k.filt_layers - 1;
   for (int i = 1; i < k.filt_layers; ++i) up.layer(c->filt_hid.l[i - 1], filt[i], prec);
   up.vec(c->filt_out, filt[k.filt_layers]);
@@ -289,7 +304,7 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   g.sc = gnn8 ? gnn_state_scales(k.gnn_iters, eab, oab) : GnnScale{};
   up.layer(g.node_enc1, ne1, pn);
   up.layer(g.node_enc2, ne2, pn);
-  up.layer(g.edge_enc1, ee1, pn);
+  up.layer(g.edge_enc1, pn == TRK_PREC_BF16 ? mean_diff_form(ee1, 3) : ee1, pn);   // (edge_encode_kernel)
   up.layer(g.edge_enc2, ee2, pn);
   up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec_gnn, g.sc.e);
   up.layer(g.edge_ab, eab, pn);

@@ -5,7 +5,10 @@ and inputs and evaluates the products in float64, so that a kernel mistake in
 fragment layout or scaling shows up as a large error while legitimate
 differences (float32 accumulation order, the tanh approximation, an activation
 that lands on the other side of an E4M3 rounding boundary) stay small:
-  * narrow first layers: inputs and weights rounded to bfloat16 (nearest even);
+  * narrow first layers: inputs and weights rounded to bfloat16 (nearest even); a
+    layer that reads both ends of an edge takes their float32 mean and difference
+    [(u_s + u_t) / 2, u_s - u_t] with the weights [W_s + W_t; (W_s - W_t) / 2]
+    (formed in float64, stored as float32), as the kernels do;
   * hidden layers: weights W * s rounded to E4M3 with s the largest power of two
     such that max|W| * s <= 448; the activations they read, 256 * tanh(.), rounded
     to E4M3; the product is divided by 256 s;
@@ -45,6 +48,17 @@ def _bf16_layer(u, w, b):
     return bf16(u) @ bf16(w) + np.asarray(b, np.float64)
 
 
+def _bf16_pair_layer(u_s, u_t, w, b):
+    """A BF16 first layer over both ends of an edge, in its mean/difference form."""
+    u_s = np.asarray(u_s, np.float32)
+    u_t = np.asarray(u_t, np.float32)
+    u = np.concatenate([np.float32(0.5) * (u_s + u_t), u_s - u_t], axis=1)
+    w = np.asarray(w, np.float64)
+    D = u_s.shape[1]
+    wm = np.concatenate([w[:D] + w[D:2 * D], 0.5 * (w[:D] - w[D:2 * D])]).astype(np.float32)
+    return _bf16_layer(u, wm, b)
+
+
 def embed_fp8(x, nets):
     layers = nets["emb"]
     h = np.tanh(_bf16_layer(x, *layers[0]))
@@ -56,8 +70,7 @@ def embed_fp8(x, nets):
 def filter_fp8(emb, src, dst, nets):
     layers = nets["filt"]
     e = np.asarray(emb, np.float32)
-    u = np.concatenate([e[src], e[dst]], axis=1)
-    h = np.tanh(_bf16_layer(u, *layers[0]))
+    h = np.tanh(_bf16_pair_layer(e[src], e[dst], *layers[0]))
     for w, b in layers[1:-1]:
         h = np.tanh(_fp8_layer(h, w, b))
     w, b = layers[-1]
@@ -113,8 +126,7 @@ def gnn_fp8(x, src, dst, nets, iters):
 
     h = np.tanh(bf16(np.tanh(_bf16_layer(x, n1w, n1b))) @ bf16(n2w) + f64(n2b))
     pj = proj(h, ew1 if iters > 0 else ow1)
-    u = np.concatenate([x[src], x[dst]], axis=1)
-    e = _q(np.tanh(bf16(np.tanh(_bf16_layer(u, e1w, e1b))) @ bf16(e2w) + f64(e2b)), se)
+    e = _q(np.tanh(bf16(np.tanh(_bf16_pair_layer(x[src], x[dst], e1w, e1b))) @ bf16(e2w) + f64(e2b)), se)
     wc, w2, woc = _fp8_w(ew1[2 * H:]), _fp8_w(ew2), _fp8_w(ow1[2 * H:])
     n = x.shape[0]
     for it in range(iters):
