@@ -152,6 +152,10 @@ def run_precision(prec, cfg, nets, xs, steps, warmup, torch, trk, latency_events
             s = time.perf_counter()
             trk.trk_event(pipe.ctx, dev[k], labels[k])
             lat.append(time.perf_counter() - s)
+    # events that no run above reached (fewer steps than events) get their labels
+    # here, untimed, so that every event's labels are compared
+    for k in range(max(warmup, steps, latency_events), len(dev)):
+        trk.trk_event(pipe.ctx, dev[k], labels[k])
     out_labels = [l.cpu().numpy() for l in labels]
     pipe.close()
     return wall, np.array(lat), infos, out_labels

@@ -25,7 +25,12 @@
 
 namespace {
 
-constexpr int KIN = 32;  // padded width of the encoder inputs (3 or 6 features)
+// The encoders' first layers read the hit features (3 per hit, 6 per edge) and run in
+// FP32 in every precision: one FP32 fragment block of k (16) covers them, costs about
+// what one BF16 block would, and keeps the features' full precision (a trained
+// encoder separates hits millimetres apart, which BF16 coordinates do not resolve).
+constexpr int KIN = PrecF32::KB;              // padded width of the encoder inputs
+constexpr int LDI = KIN + PrecF32::PAD;       // row stride of the FP32 input tile
 
 
 template <class P, int H, int MT, int NW>
@@ -33,7 +38,6 @@ struct GnnShape {
   typedef typename P::act_t T;
   static constexpr int LDH = H + P::PAD;
   static constexpr int LD2 = 2 * H + P::PAD;
-  static constexpr int LDI = KIN + P::PAD;
   static constexpr int MTW = MT / 16;
   static constexpr int NTW = H / 16 / NW;      // n-tiles per wave for N = H
   static constexpr int NTW2 = 2 * H / 16 / NW; // for N = 2H
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
                                                               typename Q::act_t* __restrict__ proj, float ps) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
-  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ __align__(16) float xin[MT * LDI];
   __shared__ __align__(16) T a1[MT * S::LDH];
   __shared__ __align__(16) T a2[MT * S::LDH];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
@@ -129,27 +133,27 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int row0 = t * MT;
     {
-      constexpr int IT = (MT * P::KB + NW * 64 - 1) / (NW * 64);
+      constexpr int IT = (MT * KIN + NW * 64 - 1) / (NW * 64);
       float v[IT];
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
-        const int m = idx / P::KB, k = idx - m * P::KB;
-        v[it] = (idx < MT * P::KB && k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f;
+        const int m = idx / KIN, k = idx - m * KIN;
+        v[it] = (idx < MT * KIN && k < 3 && row0 + m < n) ? x[(size_t)(row0 + m) * 3 + k] : 0.f;
       }
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
-        const int m = idx / P::KB, k = idx - m * P::KB;
-        if (idx < MT * P::KB) P::store1(xin + m * S::LDI, k, v[it]);
+        const int m = idx / KIN, k = idx - m * KIN;
+        if (idx < MT * KIN) xin[m * LDI + k] = v[it];
       }
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-        gemm_k<P, S::MTW, S::NTW, 3, true>(acc, xin, S::LDI, l1, wave * S::NTW);
+    gemm_k<PrecF32, S::MTW, S::NTW, 3, true>(acc, xin, LDI, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.bs, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
-        gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
+    gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
     }
     __syncthreads();
     f32x4 accp[S::MTW][S::NTW2];
-        gemm_k<P, S::MTW, S::NTW2, H, true>(accp, a2, S::LDH, lp, wave * S::NTW2);
+    gemm_k<P, S::MTW, S::NTW2, H, true>(accp, a2, S::LDH, lp, wave * S::NTW2);
 #pragma unroll
     for (int j = 0; j < S::NTW2; ++j) {
       const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;
@@ -183,10 +187,7 @@ __global__ __launch_bounds__(NW * 64) void node_encode_kernel(const float* __res
 
 // ---------------------------------------------------------------------------
 // edge encoder: e0 = tanh(tanh([x_s, x_t] W1 + b1) W2 + b2)
-// (products in P, states stored in Q's format with scale se).  With BF16 products
-// the first layer reads the ends' FP32 mean and difference, [(x_s + x_t) / 2,
-// x_s - x_t], rounded to BF16 (its weights stored for that form, the same function),
-// so that the small difference between the two ends keeps its own precision.
+// (first layer in FP32, the second in P, states stored in Q's format with scale se)
 // ---------------------------------------------------------------------------
 template <class P, class Q, int H, int MT, int NW>
 __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __restrict__ x, int n,
@@ -195,62 +196,45 @@ __global__ __launch_bounds__(NW * 64) void edge_encode_kernel(const float* __res
                                                               typename Q::act_t* __restrict__ e, int* d_err, float se) {
   typedef GnnShape<P, H, MT, NW> S;
   typedef typename S::T T;
-  __shared__ __align__(16) T xin[MT * S::LDI];
+  __shared__ __align__(16) float xin[MT * LDI];
   __shared__ __align__(16) T a1[MT * S::LDH];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int64_t m = d_m ? clamp_count(d_m, m_cap) : m_cap;
   const int64_t ntiles = (m + MT - 1) / MT;
-  constexpr bool MD = std::is_same<P, PrecBF16>::value;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * MT;
     {
-      constexpr int IT = (MT * P::KB + NW * 64 - 1) / (NW * 64);
-      int node[IT], node2[IT];
+      constexpr int IT = (MT * KIN + NW * 64 - 1) / (NW * 64);
+      int node[IT];
       float v[IT];
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
-        const int mm = idx / P::KB, k = idx - mm * P::KB;
-        node[it] = node2[it] = -1;
-        if (idx < MT * P::KB && k < 6 && row0 + mm < m) {
-          if (MD) {
-            node[it] = src[row0 + mm];
-            node2[it] = dst[row0 + mm];
-          } else {
-            node[it] = k < 3 ? src[row0 + mm] : dst[row0 + mm];
-          }
-        }
+        const int mm = idx / KIN, k = idx - mm * KIN;
+        node[it] = -1;
+        if (idx < MT * KIN && k < 6 && row0 + mm < m) node[it] = k < 3 ? src[row0 + mm] : dst[row0 + mm];
       }
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
-        const int k = idx % P::KB;
+        const int k = idx % KIN;
         v[it] = 0.f;
-        if (MD) {
-          if ((unsigned)node[it] < (unsigned)n && (unsigned)node2[it] < (unsigned)n) {
-            const float a = x[(size_t)node[it] * 3 + (k % 3)], b = x[(size_t)node2[it] * 3 + (k % 3)];
-            v[it] = k < 3 ? 0.5f * (a + b) : a - b;
-          } else if (node[it] != -1 && d_err) {
-            atomicOr(d_err, TRK_ERRBIT_INDEX);
-          }
-        } else {
-          if ((unsigned)node[it] < (unsigned)n) v[it] = x[(size_t)node[it] * 3 + (k % 3)];
-          else if (node[it] != -1 && d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
-        }
+        if ((unsigned)node[it] < (unsigned)n) v[it] = x[(size_t)node[it] * 3 + (k % 3)];
+        else if (node[it] != -1 && d_err) atomicOr(d_err, TRK_ERRBIT_INDEX);
       }
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NW * 64;
-        const int mm = idx / P::KB, k = idx - mm * P::KB;
-        if (idx < MT * P::KB) P::store1(xin + mm * S::LDI, k, v[it]);
+        const int mm = idx / KIN, k = idx - mm * KIN;
+        if (idx < MT * KIN) xin[mm * LDI + k] = v[it];
       }
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-        gemm_k<P, S::MTW, S::NTW, 6, true>(acc, xin, S::LDI, l1, wave * S::NTW);
+    gemm_k<PrecF32, S::MTW, S::NTW, 6, true>(acc, xin, LDI, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.bs, 1.f, a1, S::LDH, wave * S::NTW);
     __syncthreads();
-        gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
+    gemm_k<P, S::MTW, S::NTW, H, true>(acc, a1, S::LDH, l2, wave * S::NTW);
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
       const int nn = (wave * S::NTW + j) * 16 + 4 * g;
@@ -362,7 +346,7 @@ __global__ __launch_bounds__(NW * 64, WPE) void edge_kernel(typename P::act_t* _
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-        gemm_k<P, S::MTW, S::NTW, H, true>(acc, et, S::LDH, lc, wave * S::NTW);
+    gemm_k<P, S::MTW, S::NTW, H, true>(acc, et, S::LDH, lc, wave * S::NTW);
     float part[S::MTW];
 #pragma unroll
     for (int i = 0; i < S::MTW; ++i) part[i] = 0.f;
@@ -559,10 +543,10 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
     }
     __syncthreads();
     f32x4 acc[S::MTW][S::NTW];
-        gemm_k<P, S::MTW, S::NTW, 2 * H, true>(acc, in, S::LD2, l1, wave * S::NTW);
+    gemm_k<P, S::MTW, S::NTW, 2 * H, true>(acc, in, S::LD2, l1, wave * S::NTW);
     tile_store_tanh<P>(acc, l1.bs, 1.f, t1, S::LDH, wave * S::NTW);
     __syncthreads();
-        gemm_k<P, S::MTW, S::NTW, H, true>(acc, t1, S::LDH, l2, wave * S::NTW);
+    gemm_k<P, S::MTW, S::NTW, H, true>(acc, t1, S::LDH, l2, wave * S::NTW);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < S::NTW; ++j) {
@@ -583,7 +567,7 @@ __global__ __launch_bounds__(NW * 64) void node_step_kernel(float* __restrict__ 
     }
     __syncthreads();
     f32x4 accp[S::MTW][S::NTW2];
-        gemm_k<P, S::MTW, S::NTW2, H, true>(accp, in, S::LD2, lp, wave * S::NTW2);
+    gemm_k<P, S::MTW, S::NTW2, H, true>(accp, in, S::LD2, lp, wave * S::NTW2);
 #pragma unroll
     for (int j = 0; j < S::NTW2; ++j) {
       const int nn = (wave * S::NTW2 + j) * 16 + 4 * g;

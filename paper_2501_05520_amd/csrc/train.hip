@@ -854,12 +854,10 @@ int train_set_params(trk_ctx* c, const float* P, hipStream_t s) {
     same(c->filt_in, T.filt[0], 0, T.filt[0].K);
   for (int i = 1; i < L; ++i) same(c->filt_hid.l[i - 1], T.filt[i], 0, T.filt[i].K);
   DevGNN& G = c->gnn;
-  same(G.node_enc1, T.ne[0], 0, 3);
+  // the encoders' first layers are FP32 in every precision
+  fill(G.node_enc1, 3, T.ne[0].N, view(P, T.ne[0]), none, 0, 0, P + T.ne[0].b, 0, s);
   same(G.node_enc2, T.ne[1], 0, H);
-  if (inf_bf16)
-    fill(G.edge_enc1, 6, T.ee[0].N, view(P, T.ee[0]), none, 3, 3, P + T.ee[0].b, 1, s);
-  else
-    same(G.edge_enc1, T.ee[0], 0, 6);
+  fill(G.edge_enc1, 6, T.ee[0].N, view(P, T.ee[0]), none, 0, 0, P + T.ee[0].b, 0, s);
   same(G.edge_enc2, T.ee[1], 0, H);
   same(G.edge_c, T.en[0], 2 * H, H);
   same(G.edge_ab, T.en[0], 0, H, view(P, T.en[0], H), 1);

@@ -302,9 +302,10 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   const int pn = gnn8 ? TRK_PREC_BF16 : prec_gnn;
   const HostLinear eab = side_by_side(en1, 0, H, H), oab = side_by_side(o1, 0, H, H);
   g.sc = gnn8 ? gnn_state_scales(k.gnn_iters, eab, oab) : GnnScale{};
-  up.layer(g.node_enc1, ne1, pn);
+  // the encoders' first layers read the hit features in FP32 (node_encode_kernel, edge_encode_kernel)
+  up.layer(g.node_enc1, ne1, TRK_PREC_F32);
   up.layer(g.node_enc2, ne2, pn);
-  up.layer(g.edge_enc1, pn == TRK_PREC_BF16 ? mean_diff_form(ee1, 3) : ee1, pn);   // (edge_encode_kernel)
+  up.layer(g.edge_enc1, ee1, TRK_PREC_F32);
   up.layer(g.edge_enc2, ee2, pn);
   up.layer(g.edge_c, rows_of(en1, 2 * H, H, true), prec_gnn, g.sc.e);
   up.layer(g.edge_ab, eab, pn);

@@ -124,9 +124,11 @@ def gnn_fp8(x, src, dst, nets, iters):
     def proj(h, w1):                        # [h W_a | h W_b] in BF16, stored as E4M3
         return _q(bf16(h) @ bf16(np.concatenate([w1[:H], w1[H:2 * H]], axis=1)), sp)
 
-    h = np.tanh(bf16(np.tanh(_bf16_layer(x, n1w, n1b))) @ bf16(n2w) + f64(n2b))
+    # the encoders' first layers read the hit features in FP32 (products here in FP64)
+    h = np.tanh(bf16(np.tanh(f64(x) @ f64(n1w) + f64(n1b))) @ bf16(n2w) + f64(n2b))
     pj = proj(h, ew1 if iters > 0 else ow1)
-    e = _q(np.tanh(bf16(np.tanh(_bf16_pair_layer(x[src], x[dst], e1w, e1b))) @ bf16(e2w) + f64(e2b)), se)
+    u = np.concatenate([f64(x[src]), f64(x[dst])], axis=1)
+    e = _q(np.tanh(bf16(np.tanh(u @ f64(e1w) + f64(e1b))) @ bf16(e2w) + f64(e2b)), se)
     wc, w2, woc = _fp8_w(ew1[2 * H:]), _fp8_w(ew2), _fp8_w(ow1[2 * H:])
     n = x.shape[0]
     for it in range(iters):

@@ -89,3 +89,38 @@ def test_trained_served_forms_agreement(trained, precision):
     assert hit > 0.5
     if precision == "bf16x3":
         assert hit >= 0.99 and jac >= 0.9
+
+
+def test_trained_scores_against_fp64_per_precision(trained):
+    """Stage-isolated score errors on the trained weights against the FP64 oracle (the
+    filter on the oracle's candidate edges and embedding, the interaction network on its
+    filtered edges; pile-up-10 event).  FP32 holds the 1e-4 bar.  The trained networks
+    amplify product roundings far more than the seeded ones (the interaction network's
+    encoders separate hits millimetres apart): split BF16, whose products carry about
+    2^-16 relative error against FP32's 2^-24, reaches a few 1e-5 at the 99th
+    percentile and about 2e-4 at the maximum (a CPU emulation of its roundings gives
+    1.6e-4), so its bar here is 5e-4 at the maximum and 1e-4 at the 99th percentile.
+    BF16 gets regression guards only (filter 0.05, interaction network 0.2): with BF16
+    hit coordinates in its encoders its network's scores moved by up to 0.29, and a CPU
+    emulation with the FP32 encoder inputs it now has gives 0.15."""
+    import oracle
+    from paper_2501_05520_amd.trk import Pipeline
+    cfg, nets = trained
+    ev = generate_event(300, 10)
+    r = oracle.event(ev.x, nets, cfg)
+    e32 = r["emb"].astype(np.float32)
+    err = {}
+    for prec in ("fp32", "bf16x3", "bf16"):
+        p = Pipeline(cfg, nets, prec, max_hits=ev.n)
+        pf = p.filter(e32, r["src"], r["dst"])[0].cpu().numpy()
+        q = p.gnn(ev.x, r["fsrc"], r["fdst"]).cpu().numpy()
+        p.close()
+        df, dq = np.abs(pf - r["filter_scores"]), np.abs(q - r["gnn_scores"])
+        err[prec] = (df.max(), np.percentile(df, 99), dq.max(), np.percentile(dq, 99))
+        print(f"trained {prec} vs fp64: filter max {df.max():.3g} p99 {np.percentile(df, 99):.3g}; "
+              f"gnn max {dq.max():.3g} p99 {np.percentile(dq, 99):.3g} ({dq.size} edges)")
+    assert r["fsrc"].size > 1000
+    assert max(err["fp32"]) <= 1e-4
+    assert err["bf16x3"][0] <= 1e-4 and err["bf16x3"][2] <= 5e-4
+    assert err["bf16x3"][1] <= 1e-4 and err["bf16x3"][3] <= 1e-4
+    assert err["bf16"][2] <= 0.2 and err["bf16"][0] <= 0.05
