@@ -379,6 +379,8 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
             if idx >= warmup_requests:
                 status.append(rc)
                 lat.append(ms)
+                if requests is not None and len(lat) % 500 == 0:
+                    progress(f"  {len(lat)} of {requests} requests measured")
 
     st0 = srv.stats()
     threads = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]

@@ -186,20 +186,48 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(ActBuf X, int ldx, 
 // ---------------------------------------------------------------------------
 // wgrad: partial[chunk][k][n] = sum over the chunk's rows of X[r][k] D[r][n]; row K of
 // the output is the column sum of D when with_bias.  X is dense (ldx) or, with
-// gsrc, the pair [S[gsrc[r]], S[gdst[r]]] of width 2*gd.
+// gsrc, the pair [S[gsrc[r]], S[gdst[r]]] of width 2*gd.  Each workgroup stages
+// WG_R rows of its X and D column blocks in LDS per step; the rows are split into
+// enough chunks that several workgroups share each compute unit and hide one
+// another's load latency.
 // ---------------------------------------------------------------------------
 constexpr int WG_T = 64;   // tile edge (k and n)
 constexpr int WG_R = 64;   // rows staged per step
 
-__global__ __launch_bounds__(256) void wgrad_kernel(ActBuf X, int ldx, const int* __restrict__ gsrc,
-                                                    const int* __restrict__ gdst, const float* __restrict__ S, int gd,
-                                                    int gn, int K, int with_bias, const float* __restrict__ Dm, int ldd, int N,
-                                                    int64_t m, int64_t rows_per_chunk, float* __restrict__ partial) {
+struct WgradIn {
+  ActBuf X;
+  int ldx;
+  const int* gsrc;
+  const int* gdst;
+  const float* S;
+  int gd, gn, K, with_bias;
+  const float* D;
+  int ldd, N;
+};
+
+// element (row, k) of X and (row, n) of D (zero past rend or the widths)
+__device__ __forceinline__ void wgrad_value(const WgradIn& a, int64_t row, int64_t rend, int k, int n, float& xv,
+                                            float& dv) {
+  xv = dv = 0.f;
+  if (row >= rend) return;
+  if (k < a.K) {
+    if (a.gsrc)
+      xv = k < a.gd ? a.S[node_of(a.gsrc[row], a.gn) * a.gd + k] : a.S[node_of(a.gdst[row], a.gn) * a.gd + (k - a.gd)];
+    else
+      xv = a.X.get((size_t)row * a.ldx + k);
+  } else if (k == a.K && a.with_bias) {
+    xv = 1.f;
+  }
+  if (n < a.N) dv = a.D[(size_t)row * a.ldd + n];
+}
+
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
+                                                    float* __restrict__ partial) {
   __shared__ float xs[WG_R][WG_T + 1];
   __shared__ float ds[WG_R][WG_T + 1];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int k0 = blockIdx.x * WG_T, n0 = blockIdx.y * WG_T;
-  const int Kb = K + (with_bias ? 1 : 0);
+  const int Kb = a.K + (a.with_bias ? 1 : 0);
   const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
   const int64_t rend = min(m, rbeg + rows_per_chunk);
   f32x4 acc[4];
@@ -207,18 +235,8 @@ __global__ __launch_bounds__(256) void wgrad_kernel(ActBuf X, int ldx, const int
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
     for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
       const int rr = idx / WG_T, c = idx - rr * WG_T;
-      const int64_t row = rs + rr;
-      const int k = k0 + c, n = n0 + c;
-      float xv = 0.f, dv = 0.f;
-      if (row < rend) {
-        if (k < K) {
-          if (gsrc) xv = k < gd ? S[node_of(gsrc[row], gn) * gd + k] : S[node_of(gdst[row], gn) * gd + (k - gd)];
-          else xv = X.get((size_t)row * ldx + k);
-        } else if (k == K && with_bias) {
-          xv = 1.f;
-        }
-        if (n < N) dv = Dm[(size_t)row * ldd + n];
-      }
+      float xv, dv;
+      wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
       xs[rr][c] = xv;
       ds[rr][c] = dv;
     }
@@ -238,13 +256,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(ActBuf X, int ldx, const int
   // lane holds rows k = k0 + wave*16 + r, columns n = n0 + j*16 + 4g + c
   const int k = k0 + wave * 16 + r;
   if (k < Kb) {
-    float* P = partial + ((size_t)blockIdx.z * Kb + k) * N;
+    float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int n = n0 + j * 16 + 4 * g + c;
-        if (n < N) P[n] = acc[j][c];
+        if (n < a.N) P[n] = acc[j][c];
       }
   }
 }
@@ -254,16 +272,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(ActBuf X, int ldx, const int
 // rows of one column are one 16-byte read; 32 rows per product.
 constexpr int WGB_LD = WG_R + 8;   // row stride of the transposed tiles (bf16 elements)
 
-__global__ __launch_bounds__(256) void wgrad_bf16_kernel(ActBuf X, int ldx,
-                                                         const int* __restrict__ gsrc, const int* __restrict__ gdst,
-                                                         const float* __restrict__ S, int gd, int gn, int K,
-                                                         int with_bias, const float* __restrict__ Dm, int ldd, int N,
-                                                         int64_t m, int64_t rows_per_chunk, float* __restrict__ partial) {
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
+                                                         float* __restrict__ partial) {
   __shared__ __align__(16) __bf16 xt[WG_T][WGB_LD];
   __shared__ __align__(16) __bf16 dt[WG_T][WGB_LD];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int k0 = blockIdx.x * WG_T, n0 = blockIdx.y * WG_T;
-  const int Kb = K + (with_bias ? 1 : 0);
+  const int Kb = a.K + (a.with_bias ? 1 : 0);
   const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
   const int64_t rend = min(m, rbeg + rows_per_chunk);
   f32x4 acc[4];
@@ -271,18 +286,8 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(ActBuf X, int ldx,
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
     for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
       const int rr = idx / WG_T, c = idx - rr * WG_T;
-      const int64_t row = rs + rr;
-      const int k = k0 + c, n = n0 + c;
-      float xv = 0.f, dv = 0.f;
-      if (row < rend) {
-        if (k < K) {
-          if (gsrc) xv = k < gd ? S[node_of(gsrc[row], gn) * gd + k] : S[node_of(gdst[row], gn) * gd + (k - gd)];
-          else xv = X.get((size_t)row * ldx + k);
-        } else if (k == K && with_bias) {
-          xv = 1.f;
-        }
-        if (n < N) dv = Dm[(size_t)row * ldd + n];
-      }
+      float xv, dv;
+      wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
       xt[c][rr] = (__bf16)xv;
       dt[c][rr] = (__bf16)dv;
     }
@@ -302,13 +307,13 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(ActBuf X, int ldx,
   }
   const int k = k0 + wave * 16 + r;
   if (k < Kb) {
-    float* P = partial + ((size_t)blockIdx.z * Kb + k) * N;
+    float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int n = n0 + j * 16 + 4 * g + c;
-        if (n < N) P[n] = acc[j][c];
+        if (n < a.N) P[n] = acc[j][c];
       }
   }
 }
@@ -316,6 +321,7 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(ActBuf X, int ldx,
 __global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks, int64_t count, float* __restrict__ grad) {
   GRID_STRIDE(i, count) {
     float s = 0.f;
+#pragma unroll 8
     for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * count + i];
     grad[i] += s;
   }
@@ -537,6 +543,7 @@ struct TrainState {
   float *dh = nullptr, *dh2 = nullptr, *dq = nullptr, *dq1 = nullptr, *dnin = nullptr, *dP = nullptr, *tmpN = nullptr;
   float* partial = nullptr;
   int64_t partial_floats = 0;
+  int n_cu = 256;   // compute units of the context's device (the weight-gradient grids)
   float* bce_part = nullptr;
   int64_t cap_c = 0, cap_f = 0, nmax = 0;
   // embedding training
@@ -647,20 +654,30 @@ MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
   return v;
 }
 
+// the staged row tile is sized for the layer's fan-in, so that narrow layers (the
+// interaction network's, K <= 256) leave LDS for two to four workgroups per compute
+// unit, which hide one another's staging loads
+template <class P, int NTW, int MT, int KMAX>
+void rowgemm_launch(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
+                    ActBuf aux, int ldaux, int resident, hipStream_t s) {
+  const int64_t tiles = (m + MT - 1) / MT;
+  const int grid = (int)std::min<int64_t>(tiles, resident);
+  if (grid > 0)
+    rowgemm_kernel<P, NTW, MT, KMAX><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+}
+
 template <class P, int NTW>
 void rowgemm_t(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
                ActBuf aux, int ldaux, int n_cu, hipStream_t s) {
-  if (W.nkb * P::KB <= 512) {
-    const int64_t tiles = (m + 63) / 64;
-    const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
-    if (grid > 0)
-      rowgemm_kernel<P, NTW, 64, 512><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
-  } else {
-    const int64_t tiles = (m + 31) / 32;
-    const int grid = (int)std::min<int64_t>(tiles, (int64_t)n_cu * 2);
-    if (grid > 0)
-      rowgemm_kernel<P, NTW, 32, 1024><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
-  }
+  const int kpad = W.nkb * P::KB;
+  if (kpad <= 128)
+    rowgemm_launch<P, NTW, 64, 128>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 8, s);
+  else if (kpad <= 256)
+    rowgemm_launch<P, NTW, 64, 256>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 4, s);
+  else if (kpad <= 512)
+    rowgemm_launch<P, NTW, 64, 512>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
+  else
+    rowgemm_launch<P, NTW, 32, 1024>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
 }
 
 template <class P>
@@ -683,16 +700,21 @@ void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, c
            int K, bool bias, const float* D, int ldd, int N, int64_t m, float* grad, hipStream_t s) {
   const int Kb = K + (bias ? 1 : 0);
   const int64_t count = (int64_t)Kb * N;
-  int chunks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (m + 16383) / 16384));
+  // row chunks: enough workgroups to fill the chip several times over (at least 512
+  // rows per chunk, at most 256 chunks), within the partial-sum buffer; the chunk
+  // partition depends only on m and the shape, so the sums are reproducible
+  const int64_t tiles = (int64_t)((Kb + WG_T - 1) / WG_T) * ((N + WG_T - 1) / WG_T);
+  const int64_t want = std::max<int64_t>(1, (8 * (int64_t)T.n_cu + tiles - 1) / tiles);
+  int chunks = (int)std::min<int64_t>({256, want, std::max<int64_t>(1, m / 512)});
   while (chunks > 1 && (int64_t)chunks * count > T.partial_floats) --chunks;
   const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
   dim3 grid((Kb + WG_T - 1) / WG_T, (N + WG_T - 1) / WG_T, chunks);
   if (m > 0) {
+    const WgradIn a{X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N};
     if (T.bf16)
-      wgrad_bf16_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N, m, rpc,
-                                             T.partial);
+      wgrad_bf16_kernel<<<grid, 256, 0, s>>>(a, m, rpc, T.partial);
     else
-      wgrad_kernel<<<grid, 256, 0, s>>>(X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N, m, rpc, T.partial);
+      wgrad_kernel<<<grid, 256, 0, s>>>(a, m, rpc, T.partial);
     wgrad_reduce_kernel<<<blocks_for(count, 256), 256, 0, s>>>(T.partial, chunks, count, grad);
   }
 }
@@ -769,6 +791,7 @@ int train_create(trk_ctx* c) {
   a.add(T->dnin, (size_t)NH * 2 * H);
   a.add(T->dP, (size_t)NH * 2 * H);
   T->partial_floats = std::max<int64_t>((int64_t)16 * 513 * 512, (int64_t)8 * (EW + 1) * EW);
+  T->n_cu = c->n_cu;
   act(T->eact, (size_t)EL * NH * EW);
   a.add(T->edel0, (size_t)NH * EW);
   a.add(T->edel1, (size_t)NH * EW);
