@@ -62,6 +62,23 @@ struct ActBuf {
     if (bf16) ((__bf16*)p)[i] = (__bf16)v;
     else ((float*)p)[i] = v;
   }
+  // four consecutive elements from a multiple of four (16 or 8 bytes)
+  __device__ __forceinline__ float4 get4(size_t i) const {
+    if (bf16) {
+      const bf16x4 v = *(const bf16x4*)((const __bf16*)p + i);
+      return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    }
+    return *(const float4*)((const float*)p + i);
+  }
+  __device__ __forceinline__ void set4(size_t i, float4 v) const {
+    if (bf16) {
+      bf16x4 b;
+      b[0] = (__bf16)v.x; b[1] = (__bf16)v.y; b[2] = (__bf16)v.z; b[3] = (__bf16)v.w;
+      *(bf16x4*)((__bf16*)p + i) = b;
+    } else {
+      *(float4*)((float*)p + i) = v;
+    }
+  }
   // the buffer from element `off` on
   ActBuf at(size_t off) const { return ActBuf((char*)p + off * (bf16 ? 2 : 4), bf16); }
 };
@@ -140,15 +157,40 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(ActBuf X, int ldx, 
   typedef typename P::act_t T;
   constexpr int LDX = RG_KMAX + P::PAD;
   constexpr int MTW = RG_MT / 16;
+  constexpr int NT = RG_NW * 64;
   __shared__ __align__(16) T xs[RG_MT * LDX];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int kpad = W.nkb * P::KB;
   const int64_t ntiles = (m + RG_MT - 1) / RG_MT;
+  // four-element groups: X rows and widths that are multiples of four move as 16-byte
+  // (FP32) or 8-byte (BF16) loads, eight per thread in flight; outputs likewise
+  const bool vin = (K % 4 == 0) && (ldx % 4 == 0);
+  const bool vout = (N % 4 == 0) && (ldo % 4 == 0) && (epi != EPI_DTANH || ldaux % 4 == 0);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * RG_MT;
-    for (int idx = threadIdx.x; idx < RG_MT * kpad; idx += blockDim.x) {
-      const int mm = idx / kpad, k = idx - mm * kpad;
-      xs[mm * LDX + k] = P::cvt((row0 + mm < m && k < K) ? X.get((size_t)(row0 + mm) * ldx + k) : 0.f);
+    if (vin) {
+      const int kq = kpad / 4;
+      for (int base = threadIdx.x; base < RG_MT * kq; base += 8 * NT) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + u * NT;
+          const int mm = idx / kq, k = (idx - mm * kq) * 4;
+          v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (idx < RG_MT * kq && row0 + mm < m && k < K) v[u] = X.get4((size_t)(row0 + mm) * ldx + k);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + u * NT;
+          const int mm = idx / kq, k = (idx - mm * kq) * 4;
+          if (idx < RG_MT * kq) P::store4(xs + mm * LDX + k, v[u].x, v[u].y, v[u].z, v[u].w);
+        }
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < RG_MT * kpad; idx += blockDim.x) {
+        const int mm = idx / kpad, k = idx - mm * kpad;
+        xs[mm * LDX + k] = P::cvt((row0 + mm < m && k < K) ? X.get((size_t)(row0 + mm) * ldx + k) : 0.f);
+      }
     }
     __syncthreads();
     for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
@@ -157,6 +199,32 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(ActBuf X, int ldx, 
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
         const int n0 = (nt0 + j) * 16 + 4 * g;
+        if (vout) {
+          if (n0 >= N) continue;
+          float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (epi == EPI_BIAS || epi == EPI_BIAS_TANH) b = *(const float4*)(W.b + n0);
+#pragma unroll
+          for (int i = 0; i < MTW; ++i) {
+            const int64_t row = row0 + i * 16 + r;
+            if (row >= m) continue;
+            const size_t o = (size_t)row * ldo + n0;
+            float4 v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+            if (epi == EPI_ACC) {
+              const float4 a = out.get4(o);
+              v = make_float4(v.x + a.x, v.y + a.y, v.z + a.z, v.w + a.w);
+            } else if (epi == EPI_BIAS) {
+              v = make_float4(v.x + b.x, v.y + b.y, v.z + b.z, v.w + b.w);
+            } else if (epi == EPI_BIAS_TANH) {
+              v = make_float4(trk_tanh(v.x + b.x), trk_tanh(v.y + b.y), trk_tanh(v.z + b.z), trk_tanh(v.w + b.w));
+            } else if (epi == EPI_DTANH) {
+              const float4 a = aux.get4((size_t)row * ldaux + n0);
+              v = make_float4(v.x * (1.f - a.x * a.x), v.y * (1.f - a.y * a.y), v.z * (1.f - a.z * a.z),
+                              v.w * (1.f - a.w * a.w));
+            }
+            out.set4(o, v);
+          }
+          continue;
+        }
 #pragma unroll
         for (int i = 0; i < MTW; ++i) {
           const int64_t row = row0 + i * 16 + r;
@@ -221,6 +289,29 @@ __device__ __forceinline__ void wgrad_value(const WgradIn& a, int64_t row, int64
   if (n < a.N) dv = a.D[(size_t)row * a.ldd + n];
 }
 
+// four consecutive columns from a multiple of four: X[row][k..k+3] (or the bias
+// column) and D[row][n..n+3]; used when every width and stride is a multiple of four
+__device__ __forceinline__ void wgrad_value4(const WgradIn& a, int64_t row, int64_t rend, int k, int n, float4& xv,
+                                             float4& dv) {
+  xv = dv = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (row >= rend) return;
+  if (k < a.K) {
+    if (a.gsrc)
+      xv = k < a.gd ? *(const float4*)(a.S + node_of(a.gsrc[row], a.gn) * a.gd + k)
+                    : *(const float4*)(a.S + node_of(a.gdst[row], a.gn) * a.gd + (k - a.gd));
+    else
+      xv = a.X.get4((size_t)row * a.ldx + k);
+  } else if (k == a.K && a.with_bias) {
+    xv.x = 1.f;
+  }
+  if (n < a.N) dv = *(const float4*)(a.D + (size_t)row * a.ldd + n);
+}
+
+// whether wgrad_value4 applies
+__host__ __device__ inline bool wgrad_vec(const WgradIn& a) {
+  return a.K % 4 == 0 && a.N % 4 == 0 && a.ldd % 4 == 0 && (a.gsrc ? a.gd % 4 == 0 : a.ldx % 4 == 0);
+}
+
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
                                                     float* __restrict__ partial) {
   __shared__ float xs[WG_R][WG_T + 1];
@@ -232,13 +323,32 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
   const int64_t rend = min(m, rbeg + rows_per_chunk);
   f32x4 acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool vec = wgrad_vec(a);
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
-    for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
-      const int rr = idx / WG_T, c = idx - rr * WG_T;
-      float xv, dv;
-      wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
-      xs[rr][c] = xv;
-      ds[rr][c] = dv;
+    if (vec) {
+      // four 16-byte groups of X and of D per thread, all requested before the LDS writes
+      float4 xv[WG_R * WG_T / 1024], dv[WG_R * WG_T / 1024];
+#pragma unroll
+      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
+        const int idx = threadIdx.x + u * 256;
+        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
+        wgrad_value4(a, rs + rr, rend, k0 + c, n0 + c, xv[u], dv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
+        const int idx = threadIdx.x + u * 256;
+        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
+        xs[rr][c] = xv[u].x; xs[rr][c + 1] = xv[u].y; xs[rr][c + 2] = xv[u].z; xs[rr][c + 3] = xv[u].w;
+        ds[rr][c] = dv[u].x; ds[rr][c + 1] = dv[u].y; ds[rr][c + 2] = dv[u].z; ds[rr][c + 3] = dv[u].w;
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
+        const int rr = idx / WG_T, c = idx - rr * WG_T;
+        float xv, dv;
+        wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
+        xs[rr][c] = xv;
+        ds[rr][c] = dv;
+      }
     }
     __syncthreads();
 #pragma unroll 4
@@ -283,13 +393,33 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, i
   const int64_t rend = min(m, rbeg + rows_per_chunk);
   f32x4 acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool vec = wgrad_vec(a);
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
-    for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
-      const int rr = idx / WG_T, c = idx - rr * WG_T;
-      float xv, dv;
-      wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
-      xt[c][rr] = (__bf16)xv;
-      dt[c][rr] = (__bf16)dv;
+    if (vec) {
+      float4 xv[WG_R * WG_T / 1024], dv[WG_R * WG_T / 1024];
+#pragma unroll
+      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
+        const int idx = threadIdx.x + u * 256;
+        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
+        wgrad_value4(a, rs + rr, rend, k0 + c, n0 + c, xv[u], dv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
+        const int idx = threadIdx.x + u * 256;
+        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
+        xt[c][rr] = (__bf16)xv[u].x; xt[c + 1][rr] = (__bf16)xv[u].y;
+        xt[c + 2][rr] = (__bf16)xv[u].z; xt[c + 3][rr] = (__bf16)xv[u].w;
+        dt[c][rr] = (__bf16)dv[u].x; dt[c + 1][rr] = (__bf16)dv[u].y;
+        dt[c + 2][rr] = (__bf16)dv[u].z; dt[c + 3][rr] = (__bf16)dv[u].w;
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
+        const int rr = idx / WG_T, c = idx - rr * WG_T;
+        float xv, dv;
+        wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
+        xt[c][rr] = (__bf16)xv;
+        dt[c][rr] = (__bf16)dv;
+      }
     }
     __syncthreads();
 #pragma unroll
