@@ -93,14 +93,18 @@ static void many_clients() {
 }
 
 static void memory_admission() {
-  SleepExec ex{4, 2000, 100000};
+  // batches of 50 ms and a start gate: all eight submissions land while the first
+  // admitted requests still hold the budget, however the threads are scheduled
+  SleepExec ex{4, 50000, 100000};
   const uint64_t per_hit = 100, per_req = 0, budget = 3 * 100 * per_hit;  // three 100-hit requests
   Server<SleepExec> srv(&ex, 1, 4, 100000, budget, per_hit, per_req);
   std::vector<std::thread> th;
-  std::atomic<int> bad{0};
+  std::atomic<int> bad{0}, ready{0};
   for (int c = 0; c < 8; ++c)
     th.emplace_back([&, c] {
       auto x = make_x(100, c);
+      ++ready;
+      while (ready.load() < 8) std::this_thread::yield();
       int64_t t;
       if (srv.submit(x.data(), 100, 0.0, &t) != SERVE_OK) { ++bad; return; }
       std::vector<int32_t> lab(100);
