@@ -148,16 +148,15 @@ __global__ void bias_fill_kernel(float* out, float* out_s, int nout, const float
 // ---------------------------------------------------------------------------
 // rowgemm: out = epi(X W), X [m][K] row-major (ldx), W fragment blocks (FP32)
 // ---------------------------------------------------------------------------
-constexpr int RG_NW = 4;
 
-template <class P, int NTW, int RG_MT, int RG_KMAX>
-__global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int K, int64_t m, DevLayer W,
+template <class P, int NW, int NTW, int RG_MT, int RG_KMAX>
+__global__ __launch_bounds__(NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int K, int64_t m, DevLayer W,
                                                              ActBuf out, int ldo, int N, int epi, ActBuf aux,
                                                              int ldaux) {
   typedef typename P::act_t T;
   constexpr int LDX = RG_KMAX + P::PAD;
   constexpr int MTW = RG_MT / 16;
-  constexpr int NT = RG_NW * 64;
+  constexpr int NT = NW * 64;
   __shared__ __align__(16) T xs[RG_MT * LDX];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
   const int kpad = W.nkb * P::KB;
@@ -193,7 +192,7 @@ __global__ __launch_bounds__(RG_NW * 64) void rowgemm_kernel(ActBuf X, int ldx, 
       }
     }
     __syncthreads();
-    for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += RG_NW * NTW) {
+    for (int nt0 = wave * NTW; nt0 < W.nnt; nt0 += NW * NTW) {
       f32x4 acc[MTW][NTW];
       tile_gemm<P, MTW, NTW, true>(acc, xs, LDX, W.w, W.nkb, nt0, 0, W.nkb);
 #pragma unroll
@@ -307,6 +306,10 @@ __device__ __forceinline__ void wgrad_value4(const WgradIn& a, int64_t row, int6
   if (n < a.N) dv = *(const float4*)(a.D + (size_t)row * a.ldd + n);
 }
 
+// whether the bias row (row K of the output) is summed apart: when K fills whole k
+// tiles, a tile for that one row would cost as much as a full one
+__host__ __device__ inline bool wgrad_fold(const WgradIn& a) { return a.with_bias && a.K % WG_T == 0; }
+
 // whether wgrad_value4 applies
 __host__ __device__ inline bool wgrad_vec(const WgradIn& a) {
   return a.K % 4 == 0 && a.N % 4 == 0 && a.ldd % 4 == 0 && (a.gsrc ? a.gd % 4 == 0 : a.ldx % 4 == 0);
@@ -324,6 +327,9 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
   f32x4 acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bool vec = wgrad_vec(a);
+  // a bias row that would start a k tile of its own is summed by the first k tile
+  const bool fold = wgrad_fold(a) && blockIdx.x == 0;
+  float bsum = 0.f;
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
     if (vec) {
       // four 16-byte groups of X and of D per thread, all requested before the LDS writes
@@ -351,6 +357,8 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
       }
     }
     __syncthreads();
+    if (fold && threadIdx.x < WG_T)
+      for (int rr = 0; rr < WG_R; ++rr) bsum += ds[rr][threadIdx.x];
 #pragma unroll 4
     for (int rr = 0; rr < WG_R; rr += 4) {
       // operands: k-row fragment from X^T (row = wave*16 + r), n fragments from D
@@ -364,8 +372,10 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
     __syncthreads();
   }
   // lane holds rows k = k0 + wave*16 + r, columns n = n0 + j*16 + 4g + c
+  if (fold && threadIdx.x < WG_T && n0 + (int)threadIdx.x < a.N)
+    partial[((size_t)blockIdx.z * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
   const int k = k0 + wave * 16 + r;
-  if (k < Kb) {
+  if (k < (wgrad_fold(a) ? a.K : Kb)) {
     float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -394,6 +404,9 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, i
   f32x4 acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bool vec = wgrad_vec(a);
+  // a bias row that would start a k tile of its own is summed by the first k tile
+  const bool fold = wgrad_fold(a) && blockIdx.x == 0;
+  float bsum = 0.f;
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
     if (vec) {
       float4 xv[WG_R * WG_T / 1024], dv[WG_R * WG_T / 1024];
@@ -422,6 +435,8 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, i
       }
     }
     __syncthreads();
+    if (fold && threadIdx.x < WG_T)
+      for (int rr = 0; rr < WG_R; ++rr) bsum += (float)dt[threadIdx.x][rr];
 #pragma unroll
     for (int rr = 0; rr < WG_R; rr += 32) {
       // A: D^T rows (n = j*16 + r), B: X^T columns (k = wave*16 + r); lane group g
@@ -435,8 +450,10 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, i
     }
     __syncthreads();
   }
+  if (fold && threadIdx.x < WG_T && n0 + (int)threadIdx.x < a.N)
+    partial[((size_t)blockIdx.z * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
   const int k = k0 + wave * 16 + r;
-  if (k < Kb) {
+  if (k < (wgrad_fold(a) ? a.K : Kb)) {
     float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -475,6 +492,43 @@ __global__ void segsum_kernel(ActBuf M, int H, const int* __restrict__ p1, const
       }
       out[(size_t)node * ldo + c] = s;
     }
+  }
+}
+
+// The same sums, four columns per lane (16-byte loads of FP32 rows, 8-byte of BF16):
+// LPR = H / 4 lanes per node, 64 / LPR nodes per wave; each column is summed in the
+// same order as above, so the results are identical
+template <int LPR>
+__global__ void segsum4_kernel(ActBuf M, int H, const int* __restrict__ p1, const int* __restrict__ i1,
+                               const int* __restrict__ p2, const int* __restrict__ i2, int n, float* __restrict__ out,
+                               int ldo, float sign2) {
+  constexpr int NPW = 64 / LPR;
+  const int l = lane_id();
+  const int c = (l % LPR) * 4;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  for (int base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * NPW; base < n; base += waves * NPW) {
+    const int node = base + l / LPR;
+    if (node >= n) continue;
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p1) {
+      const int kb = p1[node], ke = p1[node + 1];
+#pragma unroll 4
+      for (int k = kb; k < ke; ++k) {
+        const float4 v = M.get4((size_t)i1[k] * H + c);
+        sum.x += v.x; sum.y += v.y; sum.z += v.z; sum.w += v.w;
+      }
+    }
+    if (p2) {
+      float4 s2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      const int kb = p2[node], ke = p2[node + 1];
+#pragma unroll 4
+      for (int k = kb; k < ke; ++k) {
+        const float4 v = M.get4((size_t)i2[k] * H + c);
+        s2.x += v.x; s2.y += v.y; s2.z += v.z; s2.w += v.w;
+      }
+      sum.x += sign2 * s2.x; sum.y += sign2 * s2.y; sum.z += sign2 * s2.z; sum.w += sign2 * s2.w;
+    }
+    *(float4*)(out + (size_t)node * ldo + c) = sum;
   }
 }
 
@@ -786,37 +840,38 @@ MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
 
 // the staged row tile is sized for the layer's fan-in, so that narrow layers (the
 // interaction network's, K <= 256) leave LDS for two to four workgroups per compute
-// unit, which hide one another's staging loads
-template <class P, int NTW, int MT, int KMAX>
+// unit, which hide one another's staging loads; the wide layers (K of 512 and more),
+// whose tile leaves room for one or two workgroups, run eight waves per workgroup
+template <class P, int NW, int NTW, int MT, int KMAX>
 void rowgemm_launch(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
                     ActBuf aux, int ldaux, int resident, hipStream_t s) {
   const int64_t tiles = (m + MT - 1) / MT;
   const int grid = (int)std::min<int64_t>(tiles, resident);
   if (grid > 0)
-    rowgemm_kernel<P, NTW, MT, KMAX><<<grid, RG_NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+    rowgemm_kernel<P, NW, NTW, MT, KMAX><<<grid, NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
 }
 
-template <class P, int NTW>
-void rowgemm_t(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
-               ActBuf aux, int ldaux, int n_cu, hipStream_t s) {
-  const int kpad = W.nkb * P::KB;
-  if (kpad <= 128)
-    rowgemm_launch<P, NTW, 64, 128>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 8, s);
-  else if (kpad <= 256)
-    rowgemm_launch<P, NTW, 64, 256>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 4, s);
-  else if (kpad <= 512)
-    rowgemm_launch<P, NTW, 64, 512>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
-  else
-    rowgemm_launch<P, NTW, 32, 1024>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
+template <class P, int NW, int MT, int KMAX>
+void rowgemm_w(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
+               ActBuf aux, int ldaux, int resident, hipStream_t s) {
+  const int per_wave = (W.nnt + NW - 1) / NW;
+  if (per_wave <= 1) rowgemm_launch<P, NW, 1, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, resident, s);
+  else if (per_wave <= 2) rowgemm_launch<P, NW, 2, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, resident, s);
+  else rowgemm_launch<P, NW, 4, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, resident, s);
 }
 
 template <class P>
 void rowgemm_p(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
                ActBuf aux, int ldaux, int n_cu, hipStream_t s) {
-  const int per_wave = (W.nnt + RG_NW - 1) / RG_NW;
-  if (per_wave <= 1) rowgemm_t<P, 1>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
-  else if (per_wave <= 2) rowgemm_t<P, 2>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
-  else rowgemm_t<P, 4>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+  const int kpad = W.nkb * P::KB;
+  if (kpad <= 128)
+    rowgemm_w<P, 4, 64, 128>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 8, s);
+  else if (kpad <= 256)
+    rowgemm_w<P, 4, 64, 256>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 4, s);
+  else if (kpad <= 512)
+    rowgemm_w<P, 8, 64, 512>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
+  else
+    rowgemm_w<P, 8, 32, 1024>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
 }
 
 // out = epi(X W) with W's blocks in the training precision (bf16: BF16 blocks)
@@ -833,14 +888,15 @@ void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, c
   // row chunks: enough workgroups to fill the chip several times over (at least 512
   // rows per chunk, at most 256 chunks), within the partial-sum buffer; the chunk
   // partition depends only on m and the shape, so the sums are reproducible
-  const int64_t tiles = (int64_t)((Kb + WG_T - 1) / WG_T) * ((N + WG_T - 1) / WG_T);
+  const WgradIn a{X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N};
+  const int ktiles = ((wgrad_fold(a) ? K : Kb) + WG_T - 1) / WG_T;
+  const int64_t tiles = (int64_t)ktiles * ((N + WG_T - 1) / WG_T);
   const int64_t want = std::max<int64_t>(1, (8 * (int64_t)T.n_cu + tiles - 1) / tiles);
   int chunks = (int)std::min<int64_t>({256, want, std::max<int64_t>(1, m / 512)});
   while (chunks > 1 && (int64_t)chunks * count > T.partial_floats) --chunks;
   const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
-  dim3 grid((Kb + WG_T - 1) / WG_T, (N + WG_T - 1) / WG_T, chunks);
+  dim3 grid(ktiles, (N + WG_T - 1) / WG_T, chunks);
   if (m > 0) {
-    const WgradIn a{X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N};
     if (T.bf16)
       wgrad_bf16_kernel<<<grid, 256, 0, s>>>(a, m, rpc, T.partial);
     else
@@ -851,6 +907,15 @@ void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, c
 
 void segsum(ActBuf M, int H, const int* p1, const int* i1, const int* p2, const int* i2, int n, float* out, int ldo,
             hipStream_t s, float sign2 = 1.f) {
+  if (ldo % 4 == 0 && (H == 128 || H == 64)) {
+    // 2 (H = 128) or 4 (H = 64) nodes per wave, four waves per block
+    const int per_block = 4 * (H == 128 ? 2 : 4);
+    if (H == 128)
+      segsum4_kernel<32><<<blocks_for(n, per_block, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo, sign2);
+    else
+      segsum4_kernel<16><<<blocks_for(n, per_block, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo, sign2);
+    return;
+  }
   segsum_kernel<<<blocks_for(n, 4, 16384), 256, 0, s>>>(M, H, p1, i1, p2, i2, n, out, ldo, sign2);
 }
 
