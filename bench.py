@@ -316,7 +316,7 @@ def agreement(la, lb, min_hits=3):
 
 
 def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed=7, pool=6, mus=None, rate=None,
-               n_slots=3, max_batch_events=8, requests=None, warmup_requests=0):
+               n_slots=3, max_batch_events=8, requests=None, warmup_requests=0, budget_events=None):
     """Serving mix: client threads with Poisson arrivals submit events whose
     pile-up is drawn uniformly from `mus` (default {50, 100, 140, 200}); one
     collector harvests results.  First a burst measures the saturated rate, then
@@ -331,8 +331,13 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
     mus = list(mus or SERVE_MUS)
     progress(f"serving {precision}, pile-up {mus}, " + (f"{seconds} s" if requests is None else f"{requests} requests"))
     pools = {mu: [generate_event(9000 + 97 * mu + k, mu).x for k in range(pool)] for mu in mus}
+    # default admission: a 64 GB budget against each slot's measured bytes per hit; with
+    # budget_events, a forced-small budget of that many pile-up-200 events in flight
+    # (4 KiB per hit each), so that admission queues requests
+    per_hit = 0 if budget_events is None else 4096
+    budget = (64 << 30) if budget_events is None else int(budget_events * 110000 * per_hit)
     srv = trk.Server(cfg, nets, precision, n_slots=n_slots, max_batch_events=max_batch_events, max_batch_hits=330000,
-                     mem_budget_bytes=64 << 30)
+                     mem_budget_bytes=budget, bytes_per_hit=per_hit)
     # warm-up and saturated rate: a burst of 48 requests
     burst = [pools[mus[k % len(mus)]][k % pool] for k in range(48)]
     t0 = time.perf_counter()
@@ -403,7 +408,8 @@ def serve_load(cfg, nets, precision, seconds, load_frac, trk, n_clients=32, seed
             "mean_batch_events": round((st["batched_events"] - st0["batched_events"]) / max(nb, 1), 2),
             "max_batch_events": max_batch_events,
             "waited_for_memory": st["waited_for_memory"] - st0["waited_for_memory"],
-            "slots": n_slots, "clients": n_clients, "mix_mu": mus, "warmup_requests": warmup_requests}
+            "slots": n_slots, "clients": n_clients, "mix_mu": mus, "warmup_requests": warmup_requests,
+            "mem_budget_bytes": budget, "bytes_per_hit": per_hit or "measured per slot"}
 
 
 def service_load(cfg, nets, precision, seconds, rate, trk, n_conn=8, seed=11, pool=6, mu=200):
@@ -740,6 +746,10 @@ def main():
             result["serving_long"].append(sv)
             result["serving_long"].append(serve_load(cfg, nets, "fp32", 0, 1.0, trk, rate=sv["offered_events_per_s"],
                                                      requests=1000, warmup_requests=200))
+        # a forced-small memory budget (two and a half pile-up-200 events in flight):
+        # requests queue for admission instead of overlapping freely
+        result["serving_long"].append(serve_load(cfg, nets, "bf16", 0, 0.8, trk, requests=2000, warmup_requests=200,
+                                                 budget_events=2.5))
     if args.serving_long == "mu200":
         # pile-up-200 events only, offered half the FP32 pipeline's own rate, one slot,
         # batches of one event: 2,000 measured requests per form
@@ -751,6 +761,12 @@ def main():
             result["serving"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk)
         except trk.TrkError as e:
             result["serving"] = {"error": str(e)}
+        try:
+            # the same load under a forced-small memory budget: admission queues requests
+            result["serving_small_budget"] = serve_load(cfg, nets, "bf16", args.serve_seconds, 0.8, trk,
+                                                        budget_events=2.5)
+        except trk.TrkError as e:
+            result["serving_small_budget"] = {"error": str(e)}
         # the served BF16 forms on pile-up-200 events only, offered the plain FP32
         # pipeline's own event rate (and half of it): p99 beside the FP32 p99 (host
         # buffers, PCIe included; Poisson arrivals queue, the FP32 figure is back to

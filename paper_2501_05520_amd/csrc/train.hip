@@ -41,7 +41,17 @@
 
 namespace {
 
-enum { EPI_STORE = 0, EPI_ACC = 1, EPI_BIAS = 2, EPI_BIAS_TANH = 3, EPI_DTANH = 4 };
+enum { EPI_STORE = 0, EPI_ACC = 1, EPI_BIAS = 2, EPI_BIAS_TANH = 3, EPI_DTANH = 4, EPI_PAIR_TANH = 5,
+       EPI_RES_TANH = 6 };   // EPI_RES_TANH: out = aux + tanh(acc + b), a residual update
+
+// EPI_PAIR_TANH: out[r] = tanh(acc[r] + P[src[r]][0:N] + P[dst[r]][N:2N] + b), the first layer
+// of an edge network on [h_s, h_t, e] with its per-node projections P = [h W_a | h W_b]
+struct PairIn {
+  const float* P = nullptr;
+  const int* src = nullptr;
+  const int* dst = nullptr;
+  int n = 0;
+};
 
 }  // namespace
 
@@ -152,7 +162,7 @@ __global__ void bias_fill_kernel(float* out, float* out_s, int nout, const float
 template <class P, int NW, int NTW, int RG_MT, int RG_KMAX>
 __global__ __launch_bounds__(NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int K, int64_t m, DevLayer W,
                                                              ActBuf out, int ldo, int N, int epi, ActBuf aux,
-                                                             int ldaux) {
+                                                             int ldaux, PairIn pr) {
   typedef typename P::act_t T;
   constexpr int LDX = RG_KMAX + P::PAD;
   constexpr int MTW = RG_MT / 16;
@@ -164,7 +174,8 @@ __global__ __launch_bounds__(NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int
   // four-element groups: X rows and widths that are multiples of four move as 16-byte
   // (FP32) or 8-byte (BF16) loads, eight per thread in flight; outputs likewise
   const bool vin = (K % 4 == 0) && (ldx % 4 == 0);
-  const bool vout = (N % 4 == 0) && (ldo % 4 == 0) && (epi != EPI_DTANH || ldaux % 4 == 0);
+  const bool vout =
+      (N % 4 == 0) && (ldo % 4 == 0) && ((epi != EPI_DTANH && epi != EPI_RES_TANH) || ldaux % 4 == 0);
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * RG_MT;
     if (vin) {
@@ -201,7 +212,8 @@ __global__ __launch_bounds__(NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int
         if (vout) {
           if (n0 >= N) continue;
           float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (epi == EPI_BIAS || epi == EPI_BIAS_TANH) b = *(const float4*)(W.b + n0);
+          if (epi == EPI_BIAS || epi == EPI_BIAS_TANH || epi == EPI_PAIR_TANH || epi == EPI_RES_TANH)
+            b = *(const float4*)(W.b + n0);
 #pragma unroll
           for (int i = 0; i < MTW; ++i) {
             const int64_t row = row0 + i * 16 + r;
@@ -219,6 +231,15 @@ __global__ __launch_bounds__(NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int
               const float4 a = aux.get4((size_t)row * ldaux + n0);
               v = make_float4(v.x * (1.f - a.x * a.x), v.y * (1.f - a.y * a.y), v.z * (1.f - a.z * a.z),
                               v.w * (1.f - a.w * a.w));
+            } else if (epi == EPI_RES_TANH) {
+              const float4 a = aux.get4((size_t)row * ldaux + n0);
+              v = make_float4(a.x + trk_tanh(v.x + b.x), a.y + trk_tanh(v.y + b.y), a.z + trk_tanh(v.z + b.z),
+                              a.w + trk_tanh(v.w + b.w));
+            } else if (epi == EPI_PAIR_TANH) {
+              const float4 ps = *(const float4*)(pr.P + node_of(pr.src[row], pr.n) * 2 * N + n0);
+              const float4 pd = *(const float4*)(pr.P + node_of(pr.dst[row], pr.n) * 2 * N + N + n0);
+              v = make_float4(trk_tanh(v.x + ps.x + pd.x + b.x), trk_tanh(v.y + ps.y + pd.y + b.y),
+                              trk_tanh(v.z + ps.z + pd.z + b.z), trk_tanh(v.w + ps.w + pd.w + b.w));
             }
             out.set4(o, v);
           }
@@ -240,6 +261,12 @@ __global__ __launch_bounds__(NW * 64) void rowgemm_kernel(ActBuf X, int ldx, int
             else if (epi == EPI_DTANH) {
               const float a = aux.get((size_t)row * ldaux + n);
               v *= 1.f - a * a;
+            } else if (epi == EPI_RES_TANH) {
+              v = aux.get((size_t)row * ldaux + n) + trk_tanh(v + W.b[n]);
+            } else if (epi == EPI_PAIR_TANH) {
+              const float ps = pr.P[node_of(pr.src[row], pr.n) * 2 * N + n];
+              const float pd = pr.P[node_of(pr.dst[row], pr.n) * 2 * N + N + n];
+              v = trk_tanh(v + ps + pd + W.b[n]);
             }
             out.set(o, v);
           }
@@ -544,18 +571,6 @@ __global__ void pair_gather_kernel(const float* S, int d, int n, const int* src,
     X.set(r * ldx + c, c < d ? S[node_of(src[r], n) * d + c] : S[node_of(dst[r], n) * d + c - d]);
   }
 }
-// t = tanh(A + P[src][0:H] + P[dst][H:2H] + b)
-__global__ void pre_tanh_kernel(const float* A, const float* P, const float* b, const int* src, const int* dst, int n,
-                                int64_t m, int H, ActBuf t) {
-  GRID_STRIDE(i, m * H) {
-    const int64_t r = i / H;
-    const int c = (int)(i - r * H);
-    t.set(i, trk_tanh(A[i] + P[node_of(src[r], n) * 2 * H + c] + P[node_of(dst[r], n) * 2 * H + H + c] + b[c]));
-  }
-}
-__global__ void add_kernel(ActBuf a, const float* b, ActBuf out, int64_t count) {
-  GRID_STRIDE(i, count) out.set(i, a.get(i) + b[i]);
-}
 // out[r][0:H] = A[r], out[r][H:2H] = B[r]
 __global__ void concat_kernel(ActBuf A, const float* B, int64_t n, int H, float* out) {
   GRID_STRIDE(i, n * 2 * H) {
@@ -722,7 +737,7 @@ struct TrainState {
   // activations kept from forward to backward (BF16 in a BF16 context)
   ActBuf fx0, fact, x6, ea1, na1, hck, eck, u, eact;
   float *fdel0 = nullptr, *fdel1 = nullptr;
-  float *P = nullptr, *pre = nullptr, *t1 = nullptr, *v = nullptr;
+  float *P = nullptr, *t1 = nullptr, *v = nullptr;
   float *de = nullptr, *dpre = nullptr, *dpre1 = nullptr, *msg = nullptr, *nin = nullptr, *q1 = nullptr, *q2 = nullptr;
   float *dh = nullptr, *dh2 = nullptr, *dq = nullptr, *dq1 = nullptr, *dnin = nullptr, *dP = nullptr, *tmpN = nullptr;
   float* partial = nullptr;
@@ -844,41 +859,41 @@ MatView view(const float* P, const LayerOff& L, int r0 = 0, int trans = 0) {
 // whose tile leaves room for one or two workgroups, run eight waves per workgroup
 template <class P, int NW, int NTW, int MT, int KMAX>
 void rowgemm_launch(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
-                    ActBuf aux, int ldaux, int resident, hipStream_t s) {
+                    ActBuf aux, int ldaux, const PairIn& pr, int resident, hipStream_t s) {
   const int64_t tiles = (m + MT - 1) / MT;
   const int grid = (int)std::min<int64_t>(tiles, resident);
   if (grid > 0)
-    rowgemm_kernel<P, NW, NTW, MT, KMAX><<<grid, NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux);
+    rowgemm_kernel<P, NW, NTW, MT, KMAX><<<grid, NW * 64, 0, s>>>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr);
 }
 
 template <class P, int NW, int MT, int KMAX>
 void rowgemm_w(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
-               ActBuf aux, int ldaux, int resident, hipStream_t s) {
+               ActBuf aux, int ldaux, const PairIn& pr, int resident, hipStream_t s) {
   const int per_wave = (W.nnt + NW - 1) / NW;
-  if (per_wave <= 1) rowgemm_launch<P, NW, 1, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, resident, s);
-  else if (per_wave <= 2) rowgemm_launch<P, NW, 2, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, resident, s);
-  else rowgemm_launch<P, NW, 4, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, resident, s);
+  if (per_wave <= 1) rowgemm_launch<P, NW, 1, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, resident, s);
+  else if (per_wave <= 2) rowgemm_launch<P, NW, 2, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, resident, s);
+  else rowgemm_launch<P, NW, 4, MT, KMAX>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, resident, s);
 }
 
 template <class P>
 void rowgemm_p(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
-               ActBuf aux, int ldaux, int n_cu, hipStream_t s) {
+               ActBuf aux, int ldaux, const PairIn& pr, int n_cu, hipStream_t s) {
   const int kpad = W.nkb * P::KB;
   if (kpad <= 128)
-    rowgemm_w<P, 4, 64, 128>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 8, s);
+    rowgemm_w<P, 4, 64, 128>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, n_cu * 8, s);
   else if (kpad <= 256)
-    rowgemm_w<P, 4, 64, 256>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 4, s);
+    rowgemm_w<P, 4, 64, 256>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, n_cu * 4, s);
   else if (kpad <= 512)
-    rowgemm_w<P, 8, 64, 512>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
+    rowgemm_w<P, 8, 64, 512>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, n_cu * 2, s);
   else
-    rowgemm_w<P, 8, 32, 1024>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu * 2, s);
+    rowgemm_w<P, 8, 32, 1024>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, n_cu * 2, s);
 }
 
 // out = epi(X W) with W's blocks in the training precision (bf16: BF16 blocks)
 void rowgemm(ActBuf X, int ldx, int K, int64_t m, const DevLayer& W, ActBuf out, int ldo, int N, int epi,
-             ActBuf aux, int ldaux, int n_cu, hipStream_t s, bool bf16) {
-  if (bf16) rowgemm_p<PrecBF16>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
-  else rowgemm_p<PrecF32>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, n_cu, s);
+             ActBuf aux, int ldaux, int n_cu, hipStream_t s, bool bf16, const PairIn& pr = PairIn()) {
+  if (bf16) rowgemm_p<PrecBF16>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, n_cu, s);
+  else rowgemm_p<PrecF32>(X, ldx, K, m, W, out, ldo, N, epi, aux, ldaux, pr, n_cu, s);
 }
 
 void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, const float* S, int gd, int gn,
@@ -979,7 +994,7 @@ int train_create(trk_ctx* c) {
   act(T->eck, (size_t)(It + 1) * CF * H);
   act(T->u, (size_t)CF * H);
   a.add(T->P, (size_t)NH * 2 * H);
-  for (float** p : {&T->pre, &T->t1, &T->v, &T->de, &T->dpre, &T->dpre1}) a.add(*p, (size_t)CF * H);
+  for (float** p : {&T->t1, &T->v, &T->de, &T->dpre, &T->dpre1}) a.add(*p, (size_t)CF * H);
   a.add(T->msg, (size_t)NH * H);
   a.add(T->nin, (size_t)NH * 2 * H);
   for (float** p : {&T->q1, &T->q2, &T->dh, &T->dh2, &T->dq, &T->dq1, &T->tmpN}) a.add(*p, (size_t)NH * H);
@@ -1175,6 +1190,11 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   const int H = c->cfg.gnn_hidden, It = c->cfg.gnn_iters;
   const int nn = (int)n;
   launch_incidence(d_src, d_dst, m, nullptr, nn, g, s);
+  PairIn pair;
+  pair.P = T.P;
+  pair.src = d_src;
+  pair.dst = d_dst;
+  pair.n = nn;
   rowgemm(d_x, 3, 3, n, T.ne1, T.na1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
   rowgemm(T.na1, H, H, n, T.ne2, T.hck, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
   ew(pair_gather_kernel, m * 6, s, d_x, 3, nn, d_src, d_dst, m, T.x6, 6);
@@ -1186,22 +1206,18 @@ int trk_gnn_train_fwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
     const ActBuf h_new = T.hck.at((size_t)t * T.nmax * H);
     const ActBuf e_new = T.eck.at((size_t)t * T.cap_f * H);
     rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
-    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
-    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
-    rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
-    ew(add_kernel, m * H, s, e, T.v, e_new, m * H);
+    rowgemm(e, H, H, m, T.ec, T.t1, H, H, EPI_PAIR_TANH, nullptr, 0, c->n_cu, s, T.bf16, pair);
+    rowgemm(T.t1, H, H, m, T.e2, e_new, H, H, EPI_RES_TANH, e, H, c->n_cu, s, T.bf16);
     segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
     ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
     rowgemm(T.nin, 2 * H, 2 * H, n, T.n1, T.q1, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
-    rowgemm(T.q1, H, H, n, T.n2, T.q2, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
-    ew(add_kernel, n * H, s, h, T.q2, h_new, n * H);
+    rowgemm(T.q1, H, H, n, T.n2, h_new, H, H, EPI_RES_TANH, h, H, c->n_cu, s, T.bf16);
   }
   const ActBuf hT = T.hck.at((size_t)It * T.nmax * H);
   const ActBuf eT = T.eck.at((size_t)It * T.cap_f * H);
   rowgemm(hT, H, H, n, T.oab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
   if (m > 0) {
-    rowgemm(eT, H, H, m, T.oc, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
-    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.oc.b, d_src, d_dst, nn, m, H, T.u);
+    rowgemm(eT, H, H, m, T.oc, T.u, H, H, EPI_PAIR_TANH, nullptr, 0, c->n_cu, s, T.bf16, pair);
     rowgemm(T.u, H, H, m, T.o2, d_logits, 1, 1, EPI_BIAS, nullptr, 0, c->n_cu, s, T.bf16);
   }
   return hipGetLastError() == hipSuccess ? TRK_OK : TRK_E_DEVICE;
@@ -1220,6 +1236,11 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
   float* G = d_grads;
   const ActBuf hT = T.hck.at((size_t)It * T.nmax * H);
   const ActBuf eT = T.eck.at((size_t)It * T.cap_f * H);
+  PairIn pair;
+  pair.P = T.P;
+  pair.src = d_src;
+  pair.dst = d_dst;
+  pair.n = nn;
   // output head
   wgrad(T, T.u, H, nullptr, nullptr, nullptr, 0, 0, H, true, d_dlogits, 1, 1, m, G + T.out[1].w, s);
   float* du = T.dpre1;
@@ -1239,8 +1260,7 @@ int trk_gnn_train_bwd(trk_ctx* c, const float* d_x, int64_t n, const int32_t* d_
     const ActBuf e_new = T.eck.at((size_t)t * T.cap_f * H);
     // recompute this iteration's internals from (h^{t-1}, e^{t-1})
     rowgemm(h, H, H, n, T.eab, T.P, 2 * H, 2 * H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
-    rowgemm(e, H, H, m, T.ec, T.pre, H, H, EPI_STORE, nullptr, 0, c->n_cu, s, T.bf16);
-    ew(pre_tanh_kernel, m * H, s, T.pre, T.P, T.ec.b, d_src, d_dst, nn, m, H, T.t1);
+    rowgemm(e, H, H, m, T.ec, T.t1, H, H, EPI_PAIR_TANH, nullptr, 0, c->n_cu, s, T.bf16, pair);
     rowgemm(T.t1, H, H, m, T.e2, T.v, H, H, EPI_BIAS_TANH, nullptr, 0, c->n_cu, s, T.bf16);
     segsum(e_new, H, g.rowptr, g.rowidx, g.cscptr, g.cscidx, nn, T.msg, H, s);
     ew(concat_kernel, n * 2 * H, s, h, T.msg, n, H, T.nin);
