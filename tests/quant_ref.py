@@ -5,10 +5,12 @@ and inputs and evaluates the products in float64, so that a kernel mistake in
 fragment layout or scaling shows up as a large error while legitimate
 differences (float32 accumulation order, the tanh approximation, an activation
 that lands on the other side of an E4M3 rounding boundary) stay small:
-  * narrow first layers: inputs and weights rounded to bfloat16 (nearest even); a
-    layer that reads both ends of an edge takes their float32 mean and difference
-    [(u_s + u_t) / 2, u_s - u_t] with the weights [W_s + W_t; (W_s - W_t) / 2]
-    (formed in float64, stored as float32), as the kernels do;
+  * narrow first MLP layers: inputs and weights rounded to bfloat16 (nearest even);
+    the filter's first layer, which reads both ends of an edge, takes their float32
+    mean and difference [(u_s + u_t) / 2, u_s - u_t] with the weights
+    [W_s + W_t; (W_s - W_t) / 2] (formed in float64, stored as float32), as the
+    kernels do; the interaction network's encoders read the hit features unrounded
+    (their first layers run in FP32);
   * hidden layers: weights W * s rounded to E4M3 with s the largest power of two
     such that max|W| * s <= 448; the activations they read, 256 * tanh(.), rounded
     to E4M3; the product is divided by 256 s;
