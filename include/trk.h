@@ -56,12 +56,17 @@ typedef enum {
 
 typedef enum {
   TRK_FP32 = 0,  /* MLP and GNN matrix products in FP32 on MFMA */
-  TRK_BF16 = 1,  /* matrix products in BF16 on MFMA, FP32 accumulation; activations stored BF16 */
+  TRK_BF16 = 1,  /* matrix products in BF16 on MFMA, FP32 accumulation; activations stored BF16.
+                  * The filter's first layer reads the FP32 mean and difference of the edge's two
+                  * embeddings (rounded to BF16 after they are formed); the interaction network's
+                  * encoders take the hit features in an FP32 first layer. */
   TRK_FP8 = 2,   /* the filter MLP's hidden layers in OCP FP8 E4M3 on MFMA with FP32 accumulation:
                   * weights with one power-of-two scale per tensor (largest |w| at most 448), tanh
-                  * activations stored with the static scale 256; its first layer, the embedding
-                  * and the interaction network run as in TRK_BF16.  Needs emb_hidden and
-                  * filt_hidden divisible by 128. */
+                  * activations stored with the static scale 256; the interaction network's edge
+                  * states and per-node projections stored as E4M3 with power-of-two scales fixed
+                  * at creation from bounds, its edge-side products in FP8 and its node side in
+                  * BF16; the filter's first layer and the embedding run as in TRK_BF16.  Needs
+                  * emb_hidden and filt_hidden divisible by 128. */
   TRK_FP8_ALL = 3, /* TRK_FP8 plus the embedding MLP's hidden and output layers in FP8 */
   TRK_BF16_EMB32 = 4, /* filter and interaction network as in TRK_BF16, the embedding in FP32: the
                        * candidate graph is the FP32 one (the radius test is the step most
