@@ -231,6 +231,46 @@ def test_embedding_training_gradient(full_width):
     tc.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_filter_gradient_full_width(precision):
+    """The filter at its full width (24 -> 512 x 3 -> 1), whose 512 x 512 weight
+    gradients run on the wide-tile products: logits and every gradient against the
+    FP64 oracle on 4,000 random hit pairs of a pile-up-2 event (the filter takes any
+    edge list; FP32 to 1e-3, BF16 to its bound)."""
+    from paper_2501_05520_amd import trk
+    from paper_2501_05520_amd.training import TrainContext
+    cfg = MU200.with_(gnn_iters=1)
+    nets = make_weights(cfg, 0)
+    ev = generate_event(8, 2)
+    emb = oracle.embed(ev.x, nets).astype(np.float32)
+    rng = np.random.default_rng(4)
+    a, b = rng.integers(0, ev.n, 4000), rng.integers(0, ev.n - 1, 4000)
+    b = b + (b >= a)                              # no self-pairs
+    src, dst = np.minimum(a, b), np.maximum(a, b)
+    y = OT.edge_truth(ev.pid, src, dst)
+    y[::7] = 1.0                                  # both classes present
+    loss, z, grads = OT.filter_loss_and_grad(emb, src, dst, y, nets)
+    tc = TrainContext(cfg, nets, max_hits=4096, max_cand_edges=20000, max_kept_edges=1000, precision=precision)
+    demb, ds, dd = _dev(emb, torch.float32), _dev(src, torch.int32), _dev(dst, torch.int32)
+    logits = torch.empty(ds.numel(), device="cuda")
+    trk.trk_filter_train_fwd(tc.ctx, demb, ds, dd, logits)
+    dz = torch.empty_like(logits)
+    trk.trk_bce_with_logits(tc.ctx, logits, _dev(y, torch.float32), dz)
+    g = torch.zeros(tc.n_params, device="cuda")
+    trk.trk_filter_train_bwd(tc.ctx, demb, ds, dd, dz, g)
+    tc.close()
+    ez = np.max(np.abs(logits.cpu().numpy() - z) / np.maximum(1.0, np.abs(z)))
+    gn = _split(g.cpu().numpy(), nets)
+    errs = {(li, "W"): _rel(gn["filt"][li][0], gw) for li, (gw, gb) in enumerate(grads)}
+    errs.update({(li, "b"): _rel(gn["filt"][li][1], gb) for li, (gw, gb) in enumerate(grads)})
+    print(f"{precision} full-width filter training: logits {ez:.3g}, gradients "
+          f"{ {k: round(v, 5) for k, v in errs.items()} }")
+    if precision == "fp32":
+        assert ez <= 1e-4 and max(errs.values()) <= GRAD_RTOL
+    else:
+        assert ez <= 0.15 and max(errs.values()) <= GRAD_RTOL_BF16
+
+
 # ---------------------------------------------------------------- BF16 products
 # Each BF16 operand is within 2^-9 of its FP32 value; a gradient passes through
 # about a dozen products (forward and backward), so its norm-wise error against the

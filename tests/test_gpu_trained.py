@@ -70,10 +70,11 @@ def test_trained_served_forms_agreement(trained, precision):
     ten-event figures).  The trained chain turns differences of 1e-5 into changed
     candidates: its filter cut sits where the scores are dense (about 4,000 edges per
     event within 1e-4 of it), and a changed filtered edge moves the interaction
-    network's scores around it.  So even split BF16, whose every stage is within the
-    FP32 bars, changes about 5 % of the candidates (measured: Jaccard 0.949-0.954, hit
-    agreement 0.994-0.995); the bars below only guard that figure (hit >= 0.99,
-    Jaccard >= 0.9) and keep every form's hits mostly in their FP32 candidate."""
+    network's scores around it.  So even split BF16 changes about 3-4 % of the
+    candidates (measured: Jaccard 0.964-0.968, hit agreement 0.994-0.995; FP32 itself
+    differs from the exact chain in 0.2 % of its candidates, see the last test); the bars
+    below only guard that figure (hit >= 0.99, Jaccard >= 0.9) and keep every form's
+    hits mostly in their FP32 candidate."""
     from paper_2501_05520_amd.trk import Pipeline
     cfg, nets = trained
     ev = generate_event(201, MU200.n_collisions)
@@ -97,12 +98,13 @@ def test_trained_scores_against_fp64_per_precision(trained):
     filtered edges; pile-up-10 event).  FP32 holds the 1e-4 bar.  The trained networks
     amplify product roundings far more than the seeded ones (the interaction network's
     encoders separate hits millimetres apart): split BF16, whose products carry about
-    2^-16 relative error against FP32's 2^-24, reaches a few 1e-5 at the 99th
-    percentile and about 2e-4 at the maximum (a CPU emulation of its roundings gives
-    1.6e-4), so its bar here is 5e-4 at the maximum and 1e-4 at the 99th percentile.
-    BF16 gets regression guards only (filter 0.05, interaction network 0.2): with BF16
-    hit coordinates in its encoders its network's scores moved by up to 0.29, and a CPU
-    emulation with the FP32 encoder inputs it now has gives 0.15."""
+    2^-16 relative error against FP32's 2^-24, reaches 7.5e-5 at the 99th percentile and
+    2.9e-4 at the maximum on these weights (1.6e-4 on the shorter-trained ones, where a CPU
+    emulation of its roundings gave the same), so its bar here is 5e-4 at the maximum and
+    1e-4 at the 99th percentile.
+    BF16 gets regression guards only (filter 0.05, interaction network 0.3): its network's
+    scores move by up to 0.18 on these weights (0.15 on the shorter-trained ones; with
+    BF16 hit coordinates in its encoders they moved by up to 0.29)."""
     import oracle
     from paper_2501_05520_amd.trk import Pipeline
     cfg, nets = trained
@@ -123,4 +125,28 @@ def test_trained_scores_against_fp64_per_precision(trained):
     assert max(err["fp32"]) <= 1e-4
     assert err["bf16x3"][0] <= 1e-4 and err["bf16x3"][2] <= 5e-4
     assert err["bf16x3"][1] <= 1e-4 and err["bf16x3"][3] <= 1e-4
-    assert err["bf16"][2] <= 0.2 and err["bf16"][0] <= 0.05
+    assert err["bf16"][2] <= 0.3 and err["bf16"][0] <= 0.05
+
+
+@pytest.mark.timeout(900)
+def test_trained_fp32_against_the_exact_chain(trained):
+    """How far FP32 itself is from exact arithmetic on the trained chain at pile-up
+    200: the FP64 oracle's own chain (its own graph, cuts and components, no margin
+    substitution) against trk_event in FP32.  Reported for the record (candidate
+    exact-match Jaccard and hit agreement); the parity proper, with the GPU's decision
+    taken on margin edges, is test_trained_end_to_end_parity.  Measured: hit agreement
+    0.99953, candidate Jaccard 0.998 (the chain's thousands of margin edges make even
+    FP32 change a few candidates); asserted with a margin: hit >= 0.999, Jaccard >= 0.99."""
+    import oracle
+    from paper_2501_05520_amd.trk import Pipeline
+    cfg, nets = trained
+    ev = generate_event(202, MU200.n_collisions)
+    p = Pipeline(cfg, nets, "fp32", max_hits=ev.n)
+    lab, info = p.event(ev.x)
+    p.close()
+    r = oracle.event(ev.x, nets, cfg)
+    hit, jac = label_agreement(lab.cpu().numpy(), np.asarray(r["labels"]))
+    print(f"trained chain, FP32 against the FP64 oracle's own chain at pile-up 200: hit agreement {hit:.6f}, "
+          f"candidate jaccard {jac:.6f} (GPU {info['n_cand_edges']} / {info['n_filt_edges']} / {info['n_kept_edges']} "
+          f"edges, oracle {r['src'].size} / {r['fsrc'].size} / {int(np.sum(r['gnn_scores'] > cfg.score_cut))})")
+    assert hit >= 0.999 and jac >= 0.99
