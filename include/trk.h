@@ -58,8 +58,9 @@ typedef enum {
   TRK_FP32 = 0,  /* MLP and GNN matrix products in FP32 on MFMA */
   TRK_BF16 = 1,  /* matrix products in BF16 on MFMA, FP32 accumulation; activations stored BF16.
                   * The filter's first layer reads the FP32 mean and difference of the edge's two
-                  * embeddings (rounded to BF16 after they are formed); the interaction network's
-                  * encoders take the hit features in an FP32 first layer. */
+                  * embeddings (rounded to BF16 after they are formed); the embedding's output
+                  * layer runs in FP32 on the last hidden layer's FP32 values; the interaction
+                  * network's encoders take the hit features in an FP32 first layer. */
   TRK_FP8 = 2,   /* the filter MLP's hidden layers in OCP FP8 E4M3 on MFMA with FP32 accumulation:
                   * weights with one power-of-two scale per tensor (largest |w| at most 448), tanh
                   * activations stored with the static scale 256; the interaction network's edge

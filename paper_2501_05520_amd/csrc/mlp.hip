@@ -63,24 +63,69 @@ __global__ __launch_bounds__(NW * 64) void embed_kernel(const float* __restrict_
         tile_gemm<P0, S::MTW, S::NTW, true>(acc, xin, S::LDI, l_in.w, l_in.nkb, nt0, 0, l_in.nkb);
     tile_store_tanh<P>(acc, l_in.bs, l_in.dq, act, S::LD, nt0);
     __syncthreads();
-    for (int h = 0; h < hid.n; ++h) {
-            tile_gemm<P, S::MTW, S::NTW, true>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
+    // BF16: the output layer reads the last hidden layer's FP32 tanh values straight
+    // from the registers (FP32 products, weights in FP32 fragments), not the BF16 tile
+    const bool fold = std::is_same<P, PrecBF16>::value && hid.n > 0;
+    const int nfull = fold ? hid.n - 1 : hid.n;
+    for (int h = 0; h < nfull; ++h) {
+      tile_gemm<P, S::MTW, S::NTW, true>(acc, act, S::LD, hid.l[h].w, hid.l[h].nkb, nt0, 0, hid.l[h].nkb);
       __syncthreads();
       tile_store_tanh<P>(acc, hid.l[h].bs, hid.l[h].dq, act, S::LD, nt0);
       __syncthreads();
     }
-    // output layer: a single 16-column tile, its k range split over the waves
-    f32x4 o[S::MTW][1];
-    acc_zero(o);
-    const int per = (l_out.nkb + NW - 1) / NW;
-    const int kb0 = wave * per;
-    const int run = min(per, l_out.nkb - kb0);
-    tile_gemm<P, S::MTW, 1>(o, act, S::LD, l_out.w, l_out.nkb, 0, kb0, run);
-    __syncthreads();
+    if (fold) {
+      // The last hidden layer in two halves of each wave's columns (registers for one
+      // half at a time).  Lane (g, r) holds h[16 i + r][16 J + 4 g + c] (J = the 16-column
+      // block): for each c these are the second operand of an FP32 product over the k
+      // chunk {16 J + 4 g' + c}, whose first operand, W_out[16 J + 4 g + c][r], is
+      // component c of the FP32 fragment of k block J.
+      const DevLayer& L = hid.l[hid.n - 1];
+      const float sc = L.dq * TRK_2LOG2E;
+      constexpr int NH = S::NTW / 2 > 0 ? S::NTW / 2 : 1;
+      f32x4 o[S::MTW];
 #pragma unroll
-    for (int i = 0; i < S::MTW; ++i)
-      *(float4*)(red + ((wave * MT + i * 16 + r) * 16 + 4 * g)) =
-          make_float4(o[i][0][0], o[i][0][1], o[i][0][2], o[i][0][3]);
+      for (int i = 0; i < S::MTW; ++i) o[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+      for (int half = 0; half * NH < S::NTW; ++half) {
+        f32x4 ah[S::MTW][NH];
+        tile_gemm<P, S::MTW, NH, true>(ah, act, S::LD, L.w, L.nkb, nt0 + half * NH, 0, L.nkb);
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+          const int J = nt0 + half * NH + j;
+          const uint4 wf = l_out.w[(size_t)J * 64 + l];
+          const float4 b = *(const float4*)(L.bs + J * 16 + 4 * g);
+#pragma unroll
+          for (int i = 0; i < S::MTW; ++i) {
+            o[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(wf.x), trk_tanh_log2(fmaf(ah[i][j][0], sc, b.x)),
+                                                        o[i], 0, 0, 0);
+            o[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(wf.y), trk_tanh_log2(fmaf(ah[i][j][1], sc, b.y)),
+                                                        o[i], 0, 0, 0);
+            o[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(wf.z), trk_tanh_log2(fmaf(ah[i][j][2], sc, b.z)),
+                                                        o[i], 0, 0, 0);
+            o[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(wf.w), trk_tanh_log2(fmaf(ah[i][j][3], sc, b.w)),
+                                                        o[i], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();   // every wave has read the LDS tile the reduction buffer overlays
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i)
+        *(float4*)(red + ((wave * MT + i * 16 + r) * 16 + 4 * g)) = make_float4(o[i][0], o[i][1], o[i][2], o[i][3]);
+    }
+    if (!fold) {
+      // output layer: a single 16-column tile, its k range split over the waves
+      f32x4 o[S::MTW][1];
+      acc_zero(o);
+      const int per = (l_out.nkb + NW - 1) / NW;
+      const int kb0 = wave * per;
+      const int run = min(per, l_out.nkb - kb0);
+      tile_gemm<P, S::MTW, 1>(o, act, S::LD, l_out.w, l_out.nkb, 0, kb0, run);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < S::MTW; ++i)
+        *(float4*)(red + ((wave * MT + i * 16 + r) * 16 + 4 * g)) =
+            make_float4(o[i][0][0], o[i][0][1], o[i][0][2], o[i][0][3]);
+    }
     __syncthreads();
     for (int idx = threadIdx.x; idx < MT * D; idx += blockDim.x) {
       const int m = idx / D, c = idx - m * D;

@@ -1164,7 +1164,10 @@ int train_set_params(trk_ctx* c, const float* P, hipStream_t s) {
   }
   same(c->emb_in, T.emb[0], 0, 3);
   for (int i = 1; i < c->cfg.emb_layers; ++i) same(c->emb_hid.l[i - 1], T.emb[i], 0, T.emb[i].K);
-  same(c->emb_out, T.emb[c->cfg.emb_layers], 0, T.emb[c->cfg.emb_layers].K);
+  {  // a BF16 embedding's output layer is kept in FP32 (embed_kernel)
+    const LayerOff& o = T.emb[c->cfg.emb_layers];
+    fill(c->emb_out, o.K, o.N, view(P, o), none, 0, 0, P + o.b, c->cfg.emb_layers > 1 ? 0 : inf_bf16, s);
+  }
   if (inf_bf16)   // the BF16 first layer reads the pair's mean and difference
     fill(c->filt_in, T.filt[0].K, T.filt[0].N, view(P, T.filt[0]), none, 3, T.filt[0].K / 2, P + T.filt[0].b, 1, s);
   else

@@ -286,7 +286,9 @@ int load_weights(trk_ctx* c, const void* blob, size_t nbytes) {
   up.layer(c->emb_in, emb[0], prec_emb_in);
   c->emb_hid.n = k.emb_layers - 1;
   for (int i = 1; i < k.emb_layers; ++i) up.layer(c->emb_hid.l[i - 1], emb[i], prec_emb);
-  up.layer(c->emb_out, emb[k.emb_layers], prec_emb);
+  // a BF16 embedding's output layer runs in FP32 on the last hidden layer's FP32 values
+  // (embed_kernel)
+  up.layer(c->emb_out, emb[k.emb_layers], prec_emb == TRK_PREC_BF16 && k.emb_layers > 1 ? TRK_PREC_F32 : prec_emb);
   // a BF16 first layer reads the pair's mean and difference (filter_kernel)
   up.layer(c->filt_in, prec_in == TRK_PREC_BF16 ? mean_diff_form(filt[0], D) : filt[0], prec_in);
   c->filt_hid.n = k.filt_layers - 1;

@@ -61,6 +61,20 @@ def _bf16_pair_layer(u_s, u_t, w, b):
     return _bf16_layer(u, wm, b)
 
 
+def embed_bf16(x, nets):
+    """The BF16 embedding: every hidden layer on BF16-rounded inputs and weights, its
+    activations stored in BF16, except the last hidden layer's, which the output layer
+    reads unrounded with float32 weights (products here in float64)."""
+    layers = nets["emb"]
+    h = np.asarray(x, np.float32)
+    for w, b in layers[:-2]:
+        h = np.tanh(_bf16_layer(h, w, b))
+    w, b = layers[-2]
+    h = np.tanh(_bf16_layer(h, w, b))                  # not rounded: read in FP32
+    w, b = layers[-1]
+    return h @ np.asarray(w, np.float64) + np.asarray(b, np.float64)
+
+
 def embed_fp8(x, nets):
     layers = nets["emb"]
     h = np.tanh(_bf16_layer(x, *layers[0]))

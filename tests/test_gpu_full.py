@@ -209,6 +209,30 @@ def test_bf16_error_report(nets, mid):
     assert dpf.max() < 0.1 and dq.max() < 0.2
 
 
+def test_bf16_embedding_matches_emulation(nets, mid):
+    """The BF16 embedding kernel against a CPU emulation of the same roundings
+    (tests/quant_ref.embed_bf16: BF16 operands in the hidden layers, the output layer
+    in FP32 on the last hidden layer's unrounded values).  What legitimately differs:
+    FP32 accumulation order and the tanh evaluation (about 1e-6 relative), and the rare
+    activation that this moves across a BF16 rounding boundary (each such flip moves one
+    of 1024 inputs of the next layer by 2^-8 of itself), so the median difference must be
+    at most 1e-4, 98 % of the outputs within 2e-3 and the largest within 0.02; a fragment
+    layout or weight-form mistake moves every output by far more.  The FP64 oracle's
+    figure is reported beside it."""
+    from paper_2501_05520_amd.trk import Pipeline
+    from tests.quant_ref import embed_bf16
+    ev, r = mid
+    p = Pipeline(MU200, nets, "bf16", max_hits=8192)
+    emb = p.embed(ev.x).cpu().numpy().astype(np.float64)
+    p.close()
+    ref = embed_bf16(ev.x, nets)
+    d = np.abs(emb - ref)
+    d64 = np.abs(emb - r["emb"])
+    print(f"bf16 embedding vs emulation: median {np.median(d):.3g} within 2e-3 {np.mean(d <= 2e-3):.4f} "
+          f"max {d.max():.3g}; vs fp64 oracle: median {np.median(d64):.3g} max {d64.max():.3g}")
+    assert np.median(d) <= 1e-4 and np.mean(d <= 2e-3) >= 0.98 and d.max() <= 0.02
+
+
 # ---------------------------------------------------------------- FP8 (reported; kernel checked by emulation)
 @pytest.mark.parametrize("precision", ["fp8", "fp8all"])
 def test_fp8_error_report(nets, mid, precision):

