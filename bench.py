@@ -471,16 +471,27 @@ def service_load(cfg, nets, precision, seconds, rate, trk, n_conn=8, seed=11, po
 
 def fit_measure(cfg, nets, ev, labels_chain, torch, trk, reps=5):
     """Downstream helix fit (trk_fit) of one pile-up-200 event: on the chain's own
-    candidates and on the generator's particles as candidates (the latter also
-    gives the pT resolution against the generated values)."""
+    candidates, on the generator's particles as candidates (which gives the pT
+    resolution against the generated values) and, where the trained weights are
+    present, on the trained chain's candidates (pT against the generated value of
+    each candidate's majority particle)."""
     pipe = trk.Pipeline(cfg, nets, "fp32", max_hits=ev.n + 64)
     x = torch.as_tensor(ev.x, device="cuda")
     lab_truth = np.arange(ev.n)
     for p in np.unique(ev.pid[ev.pid > 0]):
         idx = np.flatnonzero(ev.pid == p)
         lab_truth[idx] = idx.min()
+    inputs = [("chain_candidates", labels_chain), ("generated_particles", lab_truth)]
+    if os.path.exists(TRAINED_WEIGHTS):
+        # the trained chain's own track candidates on the same event
+        from gen import load_trained
+        tcfg, tnets = load_trained(TRAINED_WEIGHTS, cfg)
+        tp = trk.Pipeline(tcfg, tnets, "fp32", max_hits=ev.n + 64)
+        lab_t, _ = tp.event(ev.x)
+        tp.close()
+        inputs.append(("trained_chain_candidates", lab_t.cpu().numpy()))
     out = {}
-    for name, lab in (("chain_candidates", labels_chain), ("generated_particles", lab_truth)):
+    for name, lab in inputs:
         l = torch.as_tensor(np.asarray(lab, np.int32), device="cuda")
         trk.trk_fit(pipe.ctx, x, l)
         torch.cuda.synchronize()
@@ -495,6 +506,28 @@ def fit_measure(cfg, nets, ev, labels_chain, torch, trk, reps=5):
             rel = par[:, 0] / ev.truth["pt"][pid] - 1.0
             out[name]["pt_rel_error_rms"] = float(np.sqrt(np.mean(rel ** 2)))
             out[name]["charge_correct"] = float(np.mean(par[:, 4] == ev.truth["q"][pid]))
+        if name == "trained_chain_candidates":
+            # candidates whose majority particle owns more than half of their hits: the
+            # fitted pT against that particle's generated pT
+            par, cl = par.cpu().numpy(), cl.cpu().numpy()
+            lab = np.asarray(lab, np.int64)
+            pid = np.asarray(ev.pid, np.int64)
+            size = np.bincount(lab, minlength=ev.n)
+            keys, cnt = np.unique(lab * (pid.max() + 1) + pid, return_counts=True)
+            kl, kp = keys // (pid.max() + 1), keys % (pid.max() + 1)
+            order = np.lexsort((-cnt, kl))                   # per label, largest count first
+            first = order[np.r_[True, kl[order][1:] != kl[order][:-1]]]
+            major = np.full(ev.n, -1, np.int64)
+            mcnt = np.zeros(ev.n, np.int64)
+            major[kl[first]], mcnt[kl[first]] = kp[first], cnt[first]
+            ok = (major[cl] > 0) & (2 * mcnt[cl] > size[cl])
+            mp = major[cl][ok] - 1
+            rels = par[ok, 0] / ev.truth["pt"][mp] - 1.0
+            qok = par[ok, 4] == ev.truth["q"][mp]
+            out[name]["matched"] = int(rels.size)
+            out[name]["pt_rel_error_median_abs"] = float(np.median(np.abs(rels))) if rels.size else None
+            out[name]["pt_rel_error_p90_abs"] = float(np.percentile(np.abs(rels), 90)) if rels.size else None
+            out[name]["charge_correct"] = float(np.mean(qok)) if qok.size else None
     pipe.close()
     return out
 
