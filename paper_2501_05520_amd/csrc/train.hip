@@ -316,11 +316,10 @@ __device__ __forceinline__ void wgrad_value(const WgradIn& a, int64_t row, int64
 }
 
 // four consecutive columns from a multiple of four: X[row][k..k+3] (or the bias
-// column) and D[row][n..n+3]; used when every width and stride is a multiple of four
-__device__ __forceinline__ void wgrad_value4(const WgradIn& a, int64_t row, int64_t rend, int k, int n, float4& xv,
-                                             float4& dv) {
-  xv = dv = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (row >= rend) return;
+// column), D[row][n..n+3]; used when every width and stride is a multiple of four
+__device__ __forceinline__ float4 wgrad_x4(const WgradIn& a, int64_t row, int64_t rend, int k) {
+  float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (row >= rend) return xv;
   if (k < a.K) {
     if (a.gsrc)
       xv = k < a.gd ? *(const float4*)(a.S + node_of(a.gsrc[row], a.gn) * a.gd + k)
@@ -330,7 +329,16 @@ __device__ __forceinline__ void wgrad_value4(const WgradIn& a, int64_t row, int6
   } else if (k == a.K && a.with_bias) {
     xv.x = 1.f;
   }
-  if (n < a.N) dv = *(const float4*)(a.D + (size_t)row * a.ldd + n);
+  return xv;
+}
+__device__ __forceinline__ float4 wgrad_d4(const WgradIn& a, int64_t row, int64_t rend, int n) {
+  if (row >= rend || n >= a.N) return make_float4(0.f, 0.f, 0.f, 0.f);
+  return *(const float4*)(a.D + (size_t)row * a.ldd + n);
+}
+__device__ __forceinline__ void wgrad_value4(const WgradIn& a, int64_t row, int64_t rend, int k, int n, float4& xv,
+                                             float4& dv) {
+  xv = wgrad_x4(a, row, rend, k);
+  dv = wgrad_d4(a, row, rend, n);
 }
 
 // whether the bias row (row K of the output) is summed apart: when K fills whole k
@@ -342,31 +350,57 @@ __host__ __device__ inline bool wgrad_vec(const WgradIn& a) {
   return a.K % 4 == 0 && a.N % 4 == 0 && a.ldd % 4 == 0 && (a.gsrc ? a.gd % 4 == 0 : a.ldx % 4 == 0);
 }
 
+// Tiles and row chunks over a one-dimensional grid.  Consecutive workgroups go to
+// the eight XCDs in turn; the ids are dealt so that every tile of one row chunk
+// lands on the same XCD, close together in time, and the chunk's rows come from
+// HBM into that XCD's L2 once instead of into all eight.  Padding ids past the
+// last chunk leave at once.
+struct WgradTile {
+  int kt, nt, chunk;
+};
+__device__ __forceinline__ bool wgrad_tile(int ktiles, int ntiles, int chunks, WgradTile& t) {
+  const int b = blockIdx.x, xcd = b & 7, slot = b >> 3;
+  const int tiles = ktiles * ntiles;
+  const int cw = slot / tiles, tl = slot - cw * tiles;
+  t.chunk = cw * 8 + xcd;
+  t.nt = tl / ktiles;
+  t.kt = tl - t.nt * ktiles;
+  return t.chunk < chunks;
+}
+inline int64_t wgrad_grid(int64_t tiles, int chunks) { return (int64_t)8 * ((chunks + 7) / 8) * tiles; }
+
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
-                                                    float* __restrict__ partial) {
+                                                    float* __restrict__ partial, int ktiles, int ntiles,
+                                                    int chunks) {
+  WgradTile tile;
+  if (!wgrad_tile(ktiles, ntiles, chunks, tile)) return;
   __shared__ float xs[WG_R][WG_T + 1];
   __shared__ float ds[WG_R][WG_T + 1];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
-  const int k0 = blockIdx.x * WG_T, n0 = blockIdx.y * WG_T;
+  const int k0 = tile.kt * WG_T, n0 = tile.nt * WG_T;
   const int Kb = a.K + (a.with_bias ? 1 : 0);
-  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t rbeg = (int64_t)tile.chunk * rows_per_chunk;
   const int64_t rend = min(m, rbeg + rows_per_chunk);
   f32x4 acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bool vec = wgrad_vec(a);
   // a bias row that would start a k tile of its own is summed by the first k tile
-  const bool fold = wgrad_fold(a) && blockIdx.x == 0;
+  const bool fold = wgrad_fold(a) && tile.kt == 0;
   float bsum = 0.f;
+  // vector path: four 16-byte groups of X and of D per thread, held in registers; the
+  // next step's are requested once the barrier after the LDS writes has passed
+  float4 xv[WG_R * WG_T / 1024], dv[WG_R * WG_T / 1024];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
+      const int idx = threadIdx.x + u * 256;
+      const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
+      wgrad_value4(a, r0 + rr, rend, k0 + c, n0 + c, xv[u], dv[u]);
+    }
+  };
+  if (vec && rbeg < rend) fetch(rbeg);
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
     if (vec) {
-      // four 16-byte groups of X and of D per thread, all requested before the LDS writes
-      float4 xv[WG_R * WG_T / 1024], dv[WG_R * WG_T / 1024];
-#pragma unroll
-      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
-        const int idx = threadIdx.x + u * 256;
-        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
-        wgrad_value4(a, rs + rr, rend, k0 + c, n0 + c, xv[u], dv[u]);
-      }
 #pragma unroll
       for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
         const int idx = threadIdx.x + u * 256;
@@ -377,13 +411,14 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
     } else {
       for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
         const int rr = idx / WG_T, c = idx - rr * WG_T;
-        float xv, dv;
-        wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv, dv);
-        xs[rr][c] = xv;
-        ds[rr][c] = dv;
+        float xv1, dv1;
+        wgrad_value(a, rs + rr, rend, k0 + c, n0 + c, xv1, dv1);
+        xs[rr][c] = xv1;
+        ds[rr][c] = dv1;
       }
     }
     __syncthreads();
+    if (vec && rs + WG_R < rend) fetch(rs + WG_R);
     if (fold && threadIdx.x < WG_T)
       for (int rr = 0; rr < WG_R; ++rr) bsum += ds[rr][threadIdx.x];
 #pragma unroll 4
@@ -400,10 +435,10 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
   }
   // lane holds rows k = k0 + wave*16 + r, columns n = n0 + j*16 + 4g + c
   if (fold && threadIdx.x < WG_T && n0 + (int)threadIdx.x < a.N)
-    partial[((size_t)blockIdx.z * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
+    partial[((size_t)tile.chunk * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
   const int k = k0 + wave * 16 + r;
   if (k < (wgrad_fold(a) ? a.K : Kb)) {
-    float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
+    float* P = partial + ((size_t)tile.chunk * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -416,42 +451,56 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradIn a, int64_t m, int64_
 
 // The same partial products with BF16 operands: the staged rows are held
 // transposed (column-major, rows contiguous), so that a lane's eight consecutive
-// rows of one column are one 16-byte read; 32 rows per product.
+// rows of one column are one 16-byte read; 32 rows per product.  Each thread of
+// the first two waves stages eight consecutive rows of four X columns, each thread
+// of the last two the same of D, and writes them as four 16-byte column runs; it
+// requests the next step's rows right after those writes.
 constexpr int WGB_LD = WG_R + 8;   // row stride of the transposed tiles (bf16 elements)
 
 __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
-                                                         float* __restrict__ partial) {
+                                                         float* __restrict__ partial, int ktiles, int ntiles,
+                                                         int chunks) {
+  WgradTile tile;
+  if (!wgrad_tile(ktiles, ntiles, chunks, tile)) return;
   __shared__ __align__(16) __bf16 xt[WG_T][WGB_LD];
   __shared__ __align__(16) __bf16 dt[WG_T][WGB_LD];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
-  const int k0 = blockIdx.x * WG_T, n0 = blockIdx.y * WG_T;
+  const int k0 = tile.kt * WG_T, n0 = tile.nt * WG_T;
   const int Kb = a.K + (a.with_bias ? 1 : 0);
-  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t rbeg = (int64_t)tile.chunk * rows_per_chunk;
   const int64_t rend = min(m, rbeg + rows_per_chunk);
   f32x4 acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bool vec = wgrad_vec(a);
   // a bias row that would start a k tile of its own is summed by the first k tile
-  const bool fold = wgrad_fold(a) && blockIdx.x == 0;
+  const bool fold = wgrad_fold(a) && tile.kt == 0;
   float bsum = 0.f;
+  static_assert(WG_R == 64 && WG_T == 64, "128 threads x 8 rows x 4 columns per operand");
+  const bool isx = threadIdx.x < 128;                  // wave-uniform
+  const int st_t = threadIdx.x & 127, cg = st_t & 15, rg = st_t >> 4;
+  // the vector path holds a step's rows in registers: the next step's are requested
+  // before the current step's products, so their latency is hidden behind them
+  float4 v[8];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      v[j] = isx ? wgrad_x4(a, r0 + 8 * rg + j, rend, k0 + 4 * cg) : wgrad_d4(a, r0 + 8 * rg + j, rend, n0 + 4 * cg);
+  };
+  if (vec && rbeg < rend) fetch(rbeg);
   for (int64_t rs = rbeg; rs < rend; rs += WG_R) {
     if (vec) {
-      float4 xv[WG_R * WG_T / 1024], dv[WG_R * WG_T / 1024];
+      __bf16 (*tile)[WGB_LD] = isx ? xt : dt;
+      bf16x8 w0, w1, w2, w3;
 #pragma unroll
-      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
-        const int idx = threadIdx.x + u * 256;
-        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
-        wgrad_value4(a, rs + rr, rend, k0 + c, n0 + c, xv[u], dv[u]);
+      for (int j = 0; j < 8; ++j) {
+        w0[j] = (__bf16)v[j].x; w1[j] = (__bf16)v[j].y;
+        w2[j] = (__bf16)v[j].z; w3[j] = (__bf16)v[j].w;
       }
-#pragma unroll
-      for (int u = 0; u < WG_R * WG_T / 1024; ++u) {
-        const int idx = threadIdx.x + u * 256;
-        const int rr = idx / (WG_T / 4), c = (idx - rr * (WG_T / 4)) * 4;
-        xt[c][rr] = (__bf16)xv[u].x; xt[c + 1][rr] = (__bf16)xv[u].y;
-        xt[c + 2][rr] = (__bf16)xv[u].z; xt[c + 3][rr] = (__bf16)xv[u].w;
-        dt[c][rr] = (__bf16)dv[u].x; dt[c + 1][rr] = (__bf16)dv[u].y;
-        dt[c + 2][rr] = (__bf16)dv[u].z; dt[c + 3][rr] = (__bf16)dv[u].w;
-      }
+      *(bf16x8*)&tile[4 * cg][8 * rg] = w0;
+      *(bf16x8*)&tile[4 * cg + 1][8 * rg] = w1;
+      *(bf16x8*)&tile[4 * cg + 2][8 * rg] = w2;
+      *(bf16x8*)&tile[4 * cg + 3][8 * rg] = w3;
+      if (rs + WG_R < rend) fetch(rs + WG_R);
     } else {
       for (int idx = threadIdx.x; idx < WG_R * WG_T; idx += blockDim.x) {
         const int rr = idx / WG_T, c = idx - rr * WG_T;
@@ -478,10 +527,10 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, i
     __syncthreads();
   }
   if (fold && threadIdx.x < WG_T && n0 + (int)threadIdx.x < a.N)
-    partial[((size_t)blockIdx.z * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
+    partial[((size_t)tile.chunk * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
   const int k = k0 + wave * 16 + r;
   if (k < (wgrad_fold(a) ? a.K : Kb)) {
-    float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
+    float* P = partial + ((size_t)tile.chunk * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -497,23 +546,26 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradIn a, int64_t m, i
 // Wave w owns k rows [32w, 32w + 32) (two 16-row blocks) and all 128 n columns (eight
 // blocks): per four staged rows it reads two X and eight D values for sixteen products.
 // Sixteen rows are staged per step, each thread staging whole 16-byte groups of four
-// columns, requested before its LDS writes.  A bias row (with_bias; K is a multiple of
+// columns.  A bias row (with_bias; K is a multiple of
 // the tile) is summed by the k tile 0 workgroups.
 constexpr int WT = 128;
 
 __global__ __launch_bounds__(256) void wgrad128_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
-                                                       float* __restrict__ partial) {
+                                                       float* __restrict__ partial, int ktiles, int ntiles,
+                                                       int chunks) {
+  WgradTile tile;
+  if (!wgrad_tile(ktiles, ntiles, chunks, tile)) return;
   constexpr int R = 16;                        // rows staged per step
   constexpr int GPT = R * (WT / 4) / 256;      // 16-byte groups per thread and operand
   constexpr int LDF = WT + 4;                  // row stride
   __shared__ __align__(16) float xs[R][LDF];
   __shared__ __align__(16) float ds[R][LDF];
   const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
-  const int k0 = blockIdx.x * WT, n0 = blockIdx.y * WT;
+  const int k0 = tile.kt * WT, n0 = tile.nt * WT;
   const int Kb = a.K + (a.with_bias ? 1 : 0);
-  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t rbeg = (int64_t)tile.chunk * rows_per_chunk;
   const int64_t rend = min(m, rbeg + rows_per_chunk);
-  const bool fold = a.with_bias && blockIdx.x == 0;
+  const bool fold = a.with_bias && tile.kt == 0;
   float bsum = 0.f;
   f32x4 acc[2][8];
 #pragma unroll
@@ -522,17 +574,22 @@ __global__ __launch_bounds__(256) void wgrad128_kernel(WgradIn a, int64_t m, int
     for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   // this thread's groups: column group cg (four columns), rows rg + 8 u
   const int cg = threadIdx.x % (WT / 4), rg = threadIdx.x / (WT / 4);
-  for (int64_t rs = rbeg; rs < rend; rs += R) {
-    float4 xv[GPT], dv[GPT];
+  // the next step's groups are requested once the barrier after the LDS writes has passed
+  float4 xv[GPT], dv[GPT];
+  auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int u = 0; u < GPT; ++u)
-      wgrad_value4(a, rs + rg + 8 * u, rend, k0 + 4 * cg, n0 + 4 * cg, xv[u], dv[u]);
+      wgrad_value4(a, r0 + rg + 8 * u, rend, k0 + 4 * cg, n0 + 4 * cg, xv[u], dv[u]);
+  };
+  if (rbeg < rend) fetch(rbeg);
+  for (int64_t rs = rbeg; rs < rend; rs += R) {
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       *(float4*)&xs[rg + 8 * u][4 * cg] = xv[u];
       *(float4*)&ds[rg + 8 * u][4 * cg] = dv[u];
     }
     __syncthreads();
+    if (rs + R < rend) fetch(rs + R);
     if (fold && threadIdx.x < WT)
       for (int rr = 0; rr < R; ++rr) bsum += ds[rr][threadIdx.x];
 #pragma unroll
@@ -550,12 +607,99 @@ __global__ __launch_bounds__(256) void wgrad128_kernel(WgradIn a, int64_t m, int
     __syncthreads();
   }
   if (fold && threadIdx.x < WT)
-    partial[((size_t)blockIdx.z * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
+    partial[((size_t)tile.chunk * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
   // lane holds k = k0 + 32 wave + 16 i + r and n = n0 + 16 j + 4 g + c
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int k = k0 + wave * 32 + i * 16 + r;
-    float* P = partial + ((size_t)blockIdx.z * Kb + k) * a.N;
+    float* P = partial + ((size_t)tile.chunk * Kb + k) * a.N;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      *(float4*)(P + n0 + j * 16 + 4 * g) = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+  }
+}
+
+// Wide layers in BF16 (K and N multiples of 128): the same 128 x 128 output tile with
+// BF16 operands, 64 rows staged per step in tiles held transposed as in the 64 x 64
+// BF16 kernel.  Thread t stages eight consecutive rows of four columns of X and the
+// same of D (column group t mod 32, row group t / 32) as four 16-byte column runs
+// each, and requests the next step's rows once the barrier after those writes has
+// passed, so that they arrive while the step's products run (a barrier waits for
+// every load still in flight).  Wave w owns k rows [32w, 32w + 32) and all 128 n
+// columns: per 32 staged rows it reads two X and eight D fragments for sixteen
+// products.  The k tile 0 workgroups sum the bias row (with_bias).
+__global__ __launch_bounds__(256) void wgrad128_bf16_kernel(WgradIn a, int64_t m, int64_t rows_per_chunk,
+                                                            float* __restrict__ partial, int ktiles, int ntiles,
+                                                            int chunks) {
+  WgradTile tile;
+  if (!wgrad_tile(ktiles, ntiles, chunks, tile)) return;
+  constexpr int R = 64;                        // rows staged per step
+  constexpr int LDB = R + 8;                   // row stride of the transposed tiles (bf16)
+  __shared__ __align__(16) __bf16 xt[WT][LDB];
+  __shared__ __align__(16) __bf16 dt[WT][LDB];
+  const int wave = threadIdx.x >> 6, l = lane_id(), g = l >> 4, r = l & 15;
+  const int k0 = tile.kt * WT, n0 = tile.nt * WT;
+  const int Kb = a.K + (a.with_bias ? 1 : 0);
+  const int64_t rbeg = (int64_t)tile.chunk * rows_per_chunk;
+  const int64_t rend = min(m, rbeg + rows_per_chunk);
+  const bool fold = a.with_bias && tile.kt == 0;
+  float bsum = 0.f;
+  f32x4 acc[2][8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  static_assert(R == 64 && WT == 128, "256 threads x 8 rows x 4 columns per operand");
+  const int cg = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  float4 xv[8], dv[8];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      xv[j] = wgrad_x4(a, r0 + 8 * rg + j, rend, k0 + 4 * cg);
+      dv[j] = wgrad_d4(a, r0 + 8 * rg + j, rend, n0 + 4 * cg);
+    }
+  };
+  auto put = [&](__bf16 (*t)[LDB], const float4 (&v)[8]) {
+    bf16x8 w0, w1, w2, w3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      w0[j] = (__bf16)v[j].x; w1[j] = (__bf16)v[j].y;
+      w2[j] = (__bf16)v[j].z; w3[j] = (__bf16)v[j].w;
+    }
+    *(bf16x8*)&t[4 * cg][8 * rg] = w0;
+    *(bf16x8*)&t[4 * cg + 1][8 * rg] = w1;
+    *(bf16x8*)&t[4 * cg + 2][8 * rg] = w2;
+    *(bf16x8*)&t[4 * cg + 3][8 * rg] = w3;
+  };
+  if (rbeg < rend) fetch(rbeg);
+  for (int64_t rs = rbeg; rs < rend; rs += R) {
+    put(xt, xv);
+    put(dt, dv);
+    __syncthreads();
+    if (rs + R < rend) fetch(rs + R);
+    if (fold && threadIdx.x < WT)
+      for (int rr = 0; rr < R; ++rr) bsum += (float)dt[threadIdx.x][rr];
+#pragma unroll
+    for (int rr = 0; rr < R; rr += 32) {
+      bf16x8 xb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) xb[i] = *(const bf16x8*)&xt[wave * 32 + i * 16 + r][rr + 8 * g];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bf16x8 da = *(const bf16x8*)&dt[j * 16 + r][rr + 8 * g];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da, xb[i], acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (fold && threadIdx.x < WT)
+    partial[((size_t)tile.chunk * Kb + a.K) * a.N + n0 + threadIdx.x] = bsum;
+  // lane holds k = k0 + 32 wave + 16 i + r and n = n0 + 16 j + 4 g + c
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int k = k0 + wave * 32 + i * 16 + r;
+    float* P = partial + ((size_t)tile.chunk * Kb + k) * a.N;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       *(float4*)(P + n0 + j * 16 + 4 * g) = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
@@ -974,17 +1118,17 @@ void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, c
   // rows per chunk, at most 256 chunks), within the partial-sum buffer; the chunk
   // partition depends only on m and the shape, so the sums are reproducible
   const WgradIn a{X, ldx, gsrc, gdst, S, gd, gn, K, bias ? 1 : 0, D, ldd, N};
-  // FP32 only: in BF16 the transposed staging writes cost what the wider tile saves
-  // (measured: filter 512 x 512 weight gradients 10.9 ms per call on 64 x 64 tiles,
-  // 11.3 ms on 128 x 128; FP32 12.0 -> 10.6 ms)
-  if (!T.bf16 && m > 0 && wgrad_vec(a) && K % WT == 0 && N % WT == 0 && K >= 2 * WT && N >= 2 * WT) {
+  // wide layers on 128 x 128 output tiles
+  if (m > 0 && wgrad_vec(a) && K % WT == 0 && N % WT == 0 && K >= 2 * WT && N >= 2 * WT) {
     const int64_t tiles = (int64_t)(K / WT) * (N / WT);
     const int64_t want = std::max<int64_t>(1, (4 * (int64_t)T.n_cu + tiles - 1) / tiles);
     int chunks = (int)std::min<int64_t>({256, want, std::max<int64_t>(1, m / 512)});
     while (chunks > 1 && (int64_t)chunks * count > T.partial_floats) --chunks;
     const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
-    dim3 grid(K / WT, N / WT, chunks);
-    wgrad128_kernel<<<grid, 256, 0, s>>>(a, m, rpc, T.partial);
+    if (T.bf16)
+      wgrad128_bf16_kernel<<<wgrad_grid(tiles, chunks), 256, 0, s>>>(a, m, rpc, T.partial, K / WT, N / WT, chunks);
+    else
+      wgrad128_kernel<<<wgrad_grid(tiles, chunks), 256, 0, s>>>(a, m, rpc, T.partial, K / WT, N / WT, chunks);
     wgrad_reduce_kernel<<<blocks_for(count, 256), 256, 0, s>>>(T.partial, chunks, count, grad);
     return;
   }
@@ -994,12 +1138,12 @@ void wgrad(TrainState& T, ActBuf X, int ldx, const int* gsrc, const int* gdst, c
   int chunks = (int)std::min<int64_t>({256, want, std::max<int64_t>(1, m / 512)});
   while (chunks > 1 && (int64_t)chunks * count > T.partial_floats) --chunks;
   const int64_t rpc = std::max<int64_t>(1, (m + chunks - 1) / chunks);
-  dim3 grid(ktiles, (N + WG_T - 1) / WG_T, chunks);
+  const int ntiles = (N + WG_T - 1) / WG_T;
   if (m > 0) {
     if (T.bf16)
-      wgrad_bf16_kernel<<<grid, 256, 0, s>>>(a, m, rpc, T.partial);
+      wgrad_bf16_kernel<<<wgrad_grid(tiles, chunks), 256, 0, s>>>(a, m, rpc, T.partial, ktiles, ntiles, chunks);
     else
-      wgrad_kernel<<<grid, 256, 0, s>>>(a, m, rpc, T.partial);
+      wgrad_kernel<<<wgrad_grid(tiles, chunks), 256, 0, s>>>(a, m, rpc, T.partial, ktiles, ntiles, chunks);
     wgrad_reduce_kernel<<<blocks_for(count, 256), 256, 0, s>>>(T.partial, chunks, count, grad);
   }
 }
