@@ -606,8 +606,9 @@ def train_measure(cfg, nets, steps, torch, trk, precision="fp32"):
             "device_memory_gb": round(held / 2**30, 2),
             "device_memory_gb_without_recompute": round((held + extra) / 2**30, 2),
             "precision": {"fp32": "fp32 (activations and master weights)",
-                          "bf16": "bf16 operands of every product, fp32 accumulation, fp32 master weights "
-                                  "and stored states"}[precision]}
+                          "bf16": "bf16 operands of every product and bf16 stored activations (hidden "
+                                  "layers, per-iteration node and edge states), fp32 accumulation, deltas, "
+                                  "master weights and Adam moments"}[precision]}
 
 
 # The paper's own figures for its served chain (Section 4), on its hardware and workload:
