@@ -352,9 +352,9 @@ __host__ __device__ inline bool wgrad_vec(const WgradIn& a) {
 
 // Tiles and row chunks over a one-dimensional grid.  Consecutive workgroups go to
 // the eight XCDs in turn; the ids are dealt so that every tile of one row chunk
-// lands on the same XCD, close together in time, and the chunk's rows come from
-// HBM into that XCD's L2 once instead of into all eight.  Padding ids past the
-// last chunk leave at once.
+// lands on the same XCD, close together in time, where the tiles share the chunk's
+// rows through that XCD's L2 (timed level with the plain order on these shapes).
+// Padding ids past the last chunk leave at once.
 struct WgradTile {
   int kt, nt, chunk;
 };
